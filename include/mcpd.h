@@ -1,0 +1,166 @@
+/*
+ * mcpd.h -- C ABI of the MI355X unbiased Markov chain pool decoder.
+ *
+ * The library estimates every clone's posterior positive probability
+ * p_i = E_pi[Z_i] under the pooled-test posterior
+ *   pi(z | y) ~ prod_i q^{z_i} (1-q)^{1-z_i} prod_j Pr{y_j | xi_j(z)}
+ * (paper, Section "Knill's Method") with lag-1 coupled pairs of the
+ * score-weighted random-scan Gibbs sampler (Section "Coupled Score-Weighted
+ * Update Gibbs Sampler", Algorithm 3), the time-averaged estimator H_{k:l}
+ * (Section "Coupled Estimator and Fixed-Budget GPU Execution"), and
+ * fixed-budget logical slots with refill and the completion-time-corrected
+ * equal-weight aggregate (Algorithm 4, Theorem 2).
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only.  Pointers marked "host" are read or written by the
+ *     CPU; the library copies inputs at the call and never keeps caller
+ *     pointers.  Outputs are caller-allocated.
+ *   - Return value 0 (MCPD_OK) on success, a negative MCPD_E* code otherwise;
+ *     mcpd_strerror() names the code and mcpd_last_error() gives the detail
+ *     of the last failure on the calling thread.  No C++ exception crosses
+ *     the ABI.  On error, outputs are unspecified.
+ *   - One instance is not thread-safe; separate instances may be used from
+ *     separate threads on separate streams.
+ *   - Results are a pure function of (instance, weights, budget, slots, k, m,
+ *     seed, options): they do not depend on launch geometry or timing.
+ */
+#ifndef MCPD_H
+#define MCPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCPD_OK 0
+#define MCPD_EINVAL (-1)   /* invalid argument (see each function)              */
+#define MCPD_ENOMEM (-2)   /* host or device allocation failed                   */
+#define MCPD_EDEVICE (-3)  /* HIP runtime error or no usable gfx950 device       */
+#define MCPD_ECAP (-4)     /* strict_cap set and a retained pair hit the cap     */
+
+#define MCPD_MAX_DEGREE 12          /* pools per clone                          */
+#define MCPD_MAX_POOL_SIZE 255      /* clones per pool                          */
+#define MCPD_MAX_CLONES (1 << 24)
+
+typedef struct mcpd_instance mcpd_instance;
+
+/* Run options.  Initialise with mcpd_run_opts_init() and override fields. */
+typedef struct mcpd_run_opts {
+    uint64_t max_steps;     /* meeting cap: 0 = none (hard limit 2^32-1 draws);
+                               else >= max(m,1): a pair not met after
+                               max(max_steps, m) draws stops with the truncated
+                               estimator and counts in cap_hits               */
+    uint32_t refill;        /* 1 = slot refill (default); 0 = one pair per slot */
+    uint32_t strict_cap;    /* 1 = return MCPD_ECAP if a retained pair was capped */
+    uint32_t hist_bins;     /* meeting-time histogram bins (default 64)       */
+    uint32_t hist_width;    /* draws per bin (default 0 = n, one sweep)        */
+    uint32_t u_hi_bits;     /* bits of U taken from the main random block
+                               (default 32; 1..32; lower values only serve to
+                               exercise the low-bit refinement in tests)      */
+    uint32_t instance_id;   /* g of the random-number counter (< 2^24), default 0 */
+    /* Optional host outputs (NULL = not wanted). */
+    uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */
+    uint64_t *slot_units;   /* [slots] S_p(N*): progress units of the retained  */
+    int64_t *bucket_sum;    /* [bucket_rows * n] sum of V_pj over slots with
+                               N*_p = row+1 (V = W * slot numerator, exact)     */
+    uint64_t *bucket_sumsq; /* [bucket_rows * n * 2] (low, high) words of the
+                               128-bit sum of V_pj^2, same grouping            */
+    uint32_t bucket_rows;   /* rows provided; must be >= the largest N*        */
+} mcpd_run_opts;
+
+/* Run statistics (all integers exact). */
+typedef struct mcpd_run_stats {
+    uint64_t progress_units;      /* draws executed on the device, including
+                                     the replayed draws of rolled-back pairs   */
+    uint64_t retained_units;      /* sum of C over retained pairs               */
+    uint64_t single_site_updates; /* over retained pairs                        */
+    uint64_t reps_started;        /* pairs started (retained + aborted)         */
+    uint64_t reps_retained;
+    uint64_t reps_aborted;        /* started pairs stopped because they could no
+                                     longer be retained (then rolled back)      */
+    uint64_t cap_hits;            /* retained pairs stopped by the cap          */
+    uint64_t zero_completion_slots; /* slots whose first pair ended beyond B   */
+    uint64_t tau_sum;             /* over retained, met pairs                   */
+    uint64_t tau_max;
+    uint64_t nstar_max;           /* largest N*_p                               */
+    uint64_t rollback_units;      /* draws replayed to roll back aborted pairs  */
+    uint64_t lanes;               /* persistent lanes of the launch             */
+    uint32_t lds_state;           /* 1 if chain state was held in LDS           */
+    uint32_t reserved;
+    double kernel_ms;             /* device time of the sampler launch          */
+} mcpd_run_stats;
+
+/* Defaults: no cap, refill on, 64 bins of n draws, u_hi_bits 32, id 0. */
+void mcpd_run_opts_init(mcpd_run_opts *opts);
+
+/* Score weights of the paper (Section "Score-Weighted Update Gibbs Sampler"):
+ * d_j pool sizes, a_j = log Pr{y_j|xi=1} - log Pr{y_j|xi=0},
+ * s_i = sum_{j in P(i)} d_j a_j, gamma = 100 n,
+ * tau_w = log gamma / (s_max - s_min) (0 if equal),
+ * w_i = (1/2) softmax(tau_w s)_i + 1/(2n).
+ * Host-only, needs no device.  Arguments as for mcpd_create; s_out may be
+ * NULL; w_out [n] host.  Errors: MCPD_EINVAL for an invalid design. */
+int mcpd_score_weights(int32_t n_clones, int32_t n_pools, const int32_t *row_ptr,
+                       const int32_t *pool_idx, const uint8_t *outcomes, double fp,
+                       double fn, double prior, double *s_out, double *w_out);
+
+/* Create an instance: the pooling design A as a clone->pool CSR and the
+ * observed pool outcomes y (Section "Knill's Method").
+ *   n_clones, n_pools  > 0 (n_clones <= MCPD_MAX_CLONES, n_pools <= 32767)
+ *   row_ptr   host [n_clones+1], row_ptr[0] = 0, non-decreasing
+ *   pool_idx  host [row_ptr[n]], strictly ascending within each row, in
+ *             [0, n_pools); at most MCPD_MAX_DEGREE per clone and at most
+ *             MCPD_MAX_POOL_SIZE clones per pool
+ *   outcomes  host [n_pools], each 0 or 1
+ *   fp, fn, prior in (0,1) (Assumption 1 needs 0 < q, alpha, beta < 1)
+ *   hip_stream  hipStream_t to order all device work, NULL = default stream
+ *   out       receives the handle
+ * The instance starts with the paper's score weights, copies its inputs to
+ * device memory and owns them until mcpd_destroy.  Errors: MCPD_EINVAL,
+ * MCPD_ENOMEM, MCPD_EDEVICE. */
+int mcpd_create(int32_t n_clones, int32_t n_pools, const int32_t *row_ptr,
+                const int32_t *pool_idx, const uint8_t *outcomes, double fp, double fn,
+                double prior, void *hip_stream, mcpd_instance **out);
+
+/* Replace the selection weights (Assumption 1: fixed before the chains
+ * start, positive).  w: host [n], finite and > 0 (normalised internally);
+ * NULL restores the score weights.  The sampled weights are the integer
+ * masses M_i / 2^32 with sum M_i = 2^32 (see mcpd_get_weights).
+ * Errors: MCPD_EINVAL (non-positive or non-finite weight), MCPD_EDEVICE. */
+int mcpd_set_weights(mcpd_instance *inst, const double *w);
+
+/* The weights actually sampled: w_exact [n] host = M_i / 2^32 (may be NULL),
+ * mass [n] host = M_i (may be NULL). */
+int mcpd_get_weights(const mcpd_instance *inst, double *w_exact, uint32_t *mass);
+
+/* Run the fixed-budget unbiased estimator (Algorithm 4 over Algorithm 3).
+ *   budget   total progress units (one coupled draw = one unit); the per-slot
+ *            horizon is B = floor(budget / slots); 0 = one pair per slot
+ *   slots    P >= 1 logical slots
+ *   k, m     averaging window k:m (the paper's k:l), 0 <= k <= m <= 2^31
+ *   seed     64-bit key of the counter-based random numbers
+ *   opts     NULL = defaults
+ *   marginals host [n]: (1/P) sum_p A_p (the completion-time-corrected
+ *            aggregate); stderr_out host [n]: sd_p(A_p)/sqrt(P) (NaN if P=1);
+ *   hist     host [opts->hist_bins] meeting-time histogram of retained pairs
+ *            (may be NULL); stats may be NULL.
+ * Errors: MCPD_EINVAL, MCPD_ENOMEM, MCPD_EDEVICE, MCPD_ECAP. */
+int mcpd_run_unbiased(mcpd_instance *inst, uint64_t budget, uint32_t slots, uint32_t k,
+                      uint32_t m, uint64_t seed, const mcpd_run_opts *opts, double *marginals,
+                      double *stderr_out, uint64_t *hist, mcpd_run_stats *stats);
+
+/* Release the instance and its device memory (NULL is a no-op). */
+void mcpd_destroy(mcpd_instance *inst);
+
+/* Static name of an error code. */
+const char *mcpd_strerror(int code);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char *mcpd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCPD_H */

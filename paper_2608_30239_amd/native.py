@@ -1,0 +1,217 @@
+"""ctypes binding of the C ABI in ``include/mcpd.h`` (``libmcpd.so``).
+
+Argument marshalling only: every step of the decoding runs in the library's
+HIP kernels and its host setup.  There is no fallback: if the library is
+missing or the device is unusable the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from typing import Optional
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmcpd.so")
+
+MCPD_OK = 0
+MCPD_EINVAL = -1
+MCPD_ENOMEM = -2
+MCPD_EDEVICE = -3
+MCPD_ECAP = -4
+
+
+class McpdError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (code {code})")
+        self.code = code
+
+
+class RunOpts(C.Structure):
+    _fields_ = [
+        ("max_steps", C.c_uint64),
+        ("refill", C.c_uint32),
+        ("strict_cap", C.c_uint32),
+        ("hist_bins", C.c_uint32),
+        ("hist_width", C.c_uint32),
+        ("u_hi_bits", C.c_uint32),
+        ("instance_id", C.c_uint32),
+        ("slot_nstar", C.c_void_p),
+        ("slot_units", C.c_void_p),
+        ("bucket_sum", C.c_void_p),
+        ("bucket_sumsq", C.c_void_p),
+        ("bucket_rows", C.c_uint32),
+    ]
+
+
+STAT_FIELDS = ("progress_units", "retained_units", "single_site_updates", "reps_started",
+               "reps_retained", "reps_aborted", "cap_hits", "zero_completion_slots", "tau_sum",
+               "tau_max", "nstar_max", "rollback_units", "lanes")
+
+
+class RunStats(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [
+        ("lds_state", C.c_uint32), ("reserved", C.c_uint32), ("kernel_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {f: int(getattr(self, f)) for f in STAT_FIELDS}
+        d["lds_state"] = int(self.lds_state)
+        d["kernel_ms"] = float(self.kernel_ms)
+        return d
+
+
+# Every symbol include/mcpd.h declares.
+EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_create", "mcpd_set_weights",
+           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_destroy", "mcpd_strerror",
+           "mcpd_last_error")
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libmcpd.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise FileNotFoundError(f"{p} is missing: build it with paper_2608_30239_amd/build.py")
+        L = C.CDLL(p)
+        vp = C.c_void_p
+        L.mcpd_run_opts_init.argtypes = [C.POINTER(RunOpts)]
+        L.mcpd_run_opts_init.restype = None
+        L.mcpd_score_weights.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, C.c_double, C.c_double,
+                                         C.c_double, vp, vp]
+        L.mcpd_create.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, C.c_double, C.c_double,
+                                  C.c_double, vp, C.POINTER(vp)]
+        L.mcpd_set_weights.argtypes = [vp, vp]
+        L.mcpd_get_weights.argtypes = [vp, vp, vp]
+        L.mcpd_run_unbiased.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                        C.c_uint64, C.POINTER(RunOpts), vp, vp, vp,
+                                        C.POINTER(RunStats)]
+        L.mcpd_destroy.argtypes = [vp]
+        L.mcpd_destroy.restype = None
+        L.mcpd_strerror.argtypes = [C.c_int]
+        L.mcpd_strerror.restype = C.c_char_p
+        L.mcpd_last_error.argtypes = []
+        L.mcpd_last_error.restype = C.c_char_p
+        _lib = L
+        return L
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc: int, where: str):
+    if rc != MCPD_OK:
+        L = load()
+        raise McpdError(rc, where, f"{L.mcpd_strerror(rc).decode()}: {L.mcpd_last_error().decode()}")
+
+
+def _design(inst):
+    return (np.ascontiguousarray(inst.row_ptr, np.int32), np.ascontiguousarray(inst.pool_idx, np.int32),
+            np.ascontiguousarray(inst.y, np.uint8))
+
+
+def mcpd_score_weights(inst):
+    rp, pi, y = _design(inst)
+    s = np.zeros(inst.n)
+    w = np.zeros(inst.n)
+    _check(load().mcpd_score_weights(inst.n, inst.m, _p(rp), _p(pi), _p(y), inst.fp, inst.fn,
+                                     inst.prior, _p(s), _p(w)), "mcpd_score_weights")
+    return s, w
+
+
+def mcpd_create(inst, stream: Optional[int] = None):
+    rp, pi, y = _design(inst)
+    h = C.c_void_p()
+    _check(load().mcpd_create(inst.n, inst.m, _p(rp), _p(pi), _p(y), inst.fp, inst.fn, inst.prior,
+                              C.c_void_p(stream) if stream else None, C.byref(h)), "mcpd_create")
+    return h
+
+
+def mcpd_set_weights(h, w=None):
+    w = None if w is None else np.ascontiguousarray(w, np.float64)
+    _check(load().mcpd_set_weights(h, _p(w)), "mcpd_set_weights")
+
+
+def mcpd_get_weights(h, n):
+    w = np.zeros(n)
+    mass = np.zeros(n, np.uint32)
+    _check(load().mcpd_get_weights(h, _p(w), _p(mass)), "mcpd_get_weights")
+    return w, mass
+
+
+def run_opts(**kw) -> RunOpts:
+    o = RunOpts()
+    load().mcpd_run_opts_init(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mcpd_run_unbiased(h, n, budget, slots, k, m, seed=0, slot_records=False, buckets=0, **opt):
+    """Returns dict(marginals, stderr, hist, stats[, slot_nstar, slot_units, bucket_sum, bucket_sumsq])."""
+    o = run_opts(**opt)
+    out = {}
+    keep = []
+    if slot_records:
+        ns = np.zeros(slots, np.uint32)
+        su = np.zeros(slots, np.uint64)
+        o.slot_nstar, o.slot_units = _p(ns).value, _p(su).value
+        out.update(slot_nstar=ns, slot_units=su)
+        keep += [ns, su]
+    if buckets:
+        b1 = np.zeros((buckets, n), np.int64)
+        b2 = np.zeros((buckets, n, 2), np.uint64)
+        o.bucket_sum, o.bucket_sumsq, o.bucket_rows = _p(b1).value, _p(b2).value, buckets
+        out.update(bucket_sum=b1, bucket_sumsq=b2)
+        keep += [b1, b2]
+    marg = np.zeros(n)
+    se = np.zeros(n)
+    hist = np.zeros(o.hist_bins, np.uint64)
+    st = RunStats()
+    _check(load().mcpd_run_unbiased(h, budget, slots, k, m, seed, C.byref(o), _p(marg), _p(se), _p(hist),
+                                    C.byref(st)), "mcpd_run_unbiased")
+    out.update(marginals=marg, stderr=se, hist=hist, stats=st.as_dict())
+    return out
+
+
+def mcpd_destroy(h):
+    if h:
+        load().mcpd_destroy(h)
+
+
+class Decoder:
+    """Owns one mcpd instance."""
+
+    def __init__(self, inst, stream: Optional[int] = None):
+        self.inst = inst
+        self.n = inst.n
+        self.h = mcpd_create(inst, stream)
+
+    def set_weights(self, w=None):
+        mcpd_set_weights(self.h, w)
+
+    def weights(self):
+        return mcpd_get_weights(self.h, self.n)
+
+    def run(self, budget, slots, k, m, seed=0, **kw):
+        return mcpd_run_unbiased(self.h, self.n, budget, slots, k, m, seed, **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            mcpd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

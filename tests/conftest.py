@@ -14,3 +14,8 @@ if HERE not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: longer CPU test")
+
+
+def pytest_runtest_logstart(nodeid, location):
+    # name the case before it runs, so a run that dies mid-test still says which
+    print(f"\n[start] {nodeid}", flush=True)

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer results (N* buckets of the exact numerators, sums of squares,
+meeting-time histograms, per-slot N* and S_p, retained-pair counters) must be
+bit-identical.  The FP64 marginals and standard errors are formed on each
+side from those integers in a different order (the oracle averages slot
+means in slot order, the library divides the per-N* sums): they must agree
+within 1e-12 relative to the scale of the estimates.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2608_30239_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+N = pytest.importorskip("paper_2608_30239_amd.native")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    N.load()
+
+
+def _expected_device_stats(orc, B, cmin):
+    """What the device must report, derived from the oracle's per-slot
+    records: a replication that can no longer be retained is never started
+    when S + max(l,1) > B, otherwise it is stopped after B - S + 1 draws and
+    replayed once with negated contributions."""
+    sret = orc["slot_sret"].astype(np.int64)
+    disc = orc["slot_disc"].astype(np.int64)
+    started_disc = (disc > 0) & (sret + cmin <= B)
+    aborted = int(started_disc.sum())
+    rollback = int(((B - sret + 1) * started_disc).sum())
+    st = orc["stats"]
+    return dict(reps_aborted=aborted, rollback_units=rollback,
+                progress_units=st["retained_units"] + 2 * rollback,
+                reps_started=st["reps_retained"] + aborted)
+
+
+def compare(inst, budget, slots, k, m, seed=0, weights=None, tol=1e-12, **opt):
+    """Run both sides and compare everything; returns (gpu, oracle)."""
+    hist_bins = opt.get("hist_bins", 64)
+    hist_width = opt.get("hist_width", 0) or inst.n
+    M = O.Model(inst, weights=weights)
+    B = budget // slots
+    cmin = max(m, 1)
+    nb = max(1, B // cmin)
+    orc = M.run(budget, slots, k, m, seed=seed, slot_records=True, buckets=nb,
+                max_steps=opt.get("max_steps", 0), refill=opt.get("refill", 1),
+                hist_bins=hist_bins, hist_width=hist_width, u_hi_bits=opt.get("u_hi_bits", 32),
+                instance_id=opt.get("instance_id", 0))
+    dec = N.Decoder(inst)
+    try:
+        if weights is not None:
+            dec.set_weights(weights)
+        w_exact, mass = dec.weights()
+        assert np.array_equal(mass, M.masses())
+        gpu = dec.run(budget, slots, k, m, seed, slot_records=True, buckets=nb, **opt)
+    finally:
+        dec.close()
+    assert np.array_equal(gpu["bucket_sum"], orc["bucket1"])
+    assert np.array_equal(gpu["bucket_sumsq"], orc["bucket2"])
+    assert np.array_equal(gpu["hist"], orc["hist"])
+    assert np.array_equal(gpu["slot_nstar"], orc["slot_nstar"])
+    assert np.array_equal(gpu["slot_units"], orc["slot_sret"])
+    gs, os_ = gpu["stats"], orc["stats"]
+    for key in ("retained_units", "single_site_updates", "reps_retained", "cap_hits",
+                "zero_completion_slots", "tau_sum", "tau_max", "nstar_max"):
+        assert gs[key] == os_[key], key
+    for key, val in _expected_device_stats(orc, B, cmin).items():
+        assert gs[key] == val, key
+    scale = max(1e-300, float(np.max(np.abs(orc["marginals"]))))
+    assert np.max(np.abs(gpu["marginals"] - orc["marginals"])) <= tol * scale
+    if slots > 1:
+        sscale = max(1e-300, float(np.max(orc["stderr"])))
+        assert np.max(np.abs(gpu["stderr"] - orc["stderr"])) <= 1e-10 * sscale
+    else:
+        assert np.all(np.isnan(gpu["stderr"])) and np.all(np.isnan(orc["stderr"]))
+    return gpu, orc
+
+
+def test_tiny_plain_one_pair_per_slot():
+    inst, rp = I.tiny_plain()
+    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed)
+    assert gpu["stats"]["reps_retained"] == rp.slots
+
+
+@pytest.mark.parametrize("slots,mult,k,m", [(1000, 2.5, 10, 50), (333, 4.0, 0, 0), (257, 3.3, 7, 7),
+                                            (64, 9.0, 0, 20), (1, 5.0, 3, 30)])
+def test_tiny_refill_ragged(slots, mult, k, m):
+    inst, _ = I.tiny_plain()
+    B = int(mult * max(m, 1))
+    gpu, orc = compare(inst, B * slots, slots, k, m, seed=3, hist_width=1)
+    if mult > 1:
+        assert gpu["stats"]["reps_retained"] > slots
+
+
+def test_refill_off_and_instance_id():
+    inst, _ = I.tiny_plain()
+    compare(inst, 4096 * 200, 4096, 10, 50, seed=5, refill=0, instance_id=77)
+
+
+def test_meeting_cap_truncation():
+    inst = I.make_instance("noisy12", 12, 6, 3, 2, 0.25, 0.25, prior=0.3, seed=3)
+    gpu, orc = compare(inst, 2000 * 30, 2000, 2, 6, seed=9, max_steps=8, hist_width=1)
+    assert orc["stats"]["cap_hits"] > 0
+
+
+def test_low_bit_refinement_path():
+    # u_hi_bits = 2 makes the high part of U tie with the threshold often,
+    # so the low-bit block decides many draws
+    inst, _ = I.tiny_plain()
+    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=2)
+    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=13)
+
+
+def test_user_weights():
+    inst, _ = I.tiny_plain()
+    w = np.linspace(1.0, 3.0, inst.n)
+    compare(inst, 2048 * 120, 2048, 10, 50, seed=4, weights=w)
+
+
+def test_degree_up_to_twelve_and_wide_pools():
+    inst = I.make_instance("deg12", 300, 200, (6, 12), 4, 0.08, 0.12, prior=4 / 300, seed=7)
+    k, m = I.window_for_sweeps(1, inst.n)
+    compare(inst, 1024 * 4 * m, 1024, k, m, seed=1)
+
+
+def test_global_state_path():
+    # too large for LDS even at 64 lanes per workgroup
+    inst = I.make_instance("big", 12000, 900, (3, 7), 6, 0.1, 0.1, prior=6 / 12000, seed=2)
+    k, m = 10, 200
+    gpu, _ = compare(inst, 512 * 700, 512, k, m, seed=6)
+    assert gpu["stats"]["lds_state"] == 0
+
+
+def test_deterministic_repeat():
+    inst, rp = I.tiny_plain()
+    dec = N.Decoder(inst)
+    try:
+        a = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3)
+        b = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3)
+    finally:
+        dec.close()
+    assert np.array_equal(a["marginals"], b["marginals"])
+    assert np.array_equal(a["bucket_sum"], b["bucket_sum"])
+    assert np.array_equal(a["hist"], b["hist"])
+
+
+def test_invalid_arguments_raise():
+    inst, _ = I.tiny_plain()
+    dec = N.Decoder(inst)
+    try:
+        with pytest.raises(N.McpdError):
+            dec.run(0, 0, 1, 2)               # slots = 0
+        with pytest.raises(N.McpdError):
+            dec.run(0, 16, 5, 4)              # k > m
+        with pytest.raises(N.McpdError):
+            dec.run(0, 16, 1, 10, max_steps=5)  # cap below m
+        with pytest.raises(N.McpdError):
+            dec.set_weights(np.zeros(inst.n))
+    finally:
+        dec.close()
+
+
+def test_paper_shaped_full_size():
+    inst, rp = I.paper_shaped()
+    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed)
+    assert gpu["stats"]["lds_state"] == 1
+    assert gpu["stats"]["nstar_max"] >= 3
