@@ -6,22 +6,51 @@
 
 namespace mcpd {
 
-// Per-instance read-only tables in device memory.
-struct DevTables {
-    const uint32_t *guide;  // [1 << gbits]: smallest i with cum_hi[i] >= b << gshift
-    const uint32_t *cum_hi; // [n]: M_0 + ... + M_i - 1 (inclusive upper bound of clone i's site words)
-    const uint16_t *rows;   // [n * R]: pool | (y << 15), ascending, padded with 0xFFFF
-    const uint64_t *thr;    // [2^(dmax+1) - 1]: floor(p * 2^53) per ordered free-pool outcome pattern
-    int32_t n, m, dmax, R;
-    uint32_t gshift;        // 32 - gbits
+// Clone records: word 0 holds the inclusive upper bound of the clone's site
+// words (M_0 + ... + M_i - 1); the following bytes hold its pools in
+// ascending order, each entry pool | (outcome << top bit), padded with
+// all-ones entries.  A format fixes the entry width and the number of
+// entries the kernel reads (a compile-time loop length).
+enum RecFmt {
+    FMT_U8_4 = 0,   // 8-byte records, 4 one-byte entries (pools < 127)
+    FMT_U8_5 = 1,   // 16-byte records, 5 one-byte entries
+    FMT_U8_8 = 2,   // 16-byte records, 8 one-byte entries
+    FMT_U8_12 = 3,  // 16-byte records, 12 one-byte entries
+    FMT_U16_4 = 4,  // 16-byte records, 4 two-byte entries (pools < 32767)
+    FMT_U16_8 = 5,  // 32-byte records, 8 two-byte entries
+    FMT_U16_12 = 6, // 32-byte records, 12 two-byte entries
+    FMT_COUNT = 7
 };
 
-// Slot-block of one launch (one instance).
+__host__ __device__ constexpr int fmt_entries(int f)
+{
+    return f == FMT_U8_4 ? 4 : f == FMT_U8_5 ? 5 : f == FMT_U8_8 ? 8 : f == FMT_U8_12 ? 12
+         : f == FMT_U16_4 ? 4 : f == FMT_U16_8 ? 8 : 12;
+}
+__host__ __device__ constexpr bool fmt_wide(int f) { return f >= FMT_U16_4; }
+__host__ __device__ constexpr int fmt_rec_bytes(int f)
+{
+    return f == FMT_U8_4 ? 8 : (f == FMT_U16_8 || f == FMT_U16_12) ? 32 : 16;
+}
+
+// Per-instance read-only tables in device memory.
+struct DevTables {
+    const uint32_t *guide;  // [1 << gbits]: smallest i with cum_hi(i) >= b << gshift
+    const uint32_t *recs;   // [n * rec_bytes / 4] clone records
+    const uint64_t *thr;    // [2^(dmax+1) - 1]: floor(p * 2^53) per ordered free-pool outcome pattern
+    int32_t n, m, dmax, fmt;
+    uint32_t gshift;        // 32 - gbits
+    uint32_t gbits;
+    uint32_t rec_bytes;
+    uint32_t thr_len;
+};
+
+// One launch (one instance).
 struct RunArgs {
     DevTables T;
     uint64_t B;         // per-slot horizon
-    uint64_t capmax;    // draws after which an unmet pair stops
     uint64_t seed;
+    uint32_t capmax;    // draws after which an unmet pair stops
     uint32_t P;         // slots
     uint32_t k, ell, W; // window
     uint32_t cmin;      // max(ell, 1): cost of the cheapest replication
@@ -31,16 +60,18 @@ struct RunArgs {
     uint32_t hist_bins, hist_width;
     uint32_t words_bits, words_cnt; // per-lane state words (bit pairs, count pairs)
     uint32_t list_cap;  // touched-list capacity per lane
+    uint32_t tab_off_thr, tab_off_guide, tab_off_recs, tab_bytes; // LDS table layout (bytes)
     uint32_t nbuckets;  // rows of S1/S2
     // per-lane storage (lanes_total = gridDim.x * blockDim.x)
-    int64_t *acc;       // [lanes_total * n] numerator rows (kept zero between slots)
+    int64_t *acc;       // [lanes_total * n] spilled numerators (kept zero between slots)
     uint32_t *lists;    // [lanes_total * list_cap]
     uint32_t *gstate;   // [lanes_total * (words_bits + words_cnt)] when state is not in LDS
+    uint64_t *lane_stats; // [lanes_total * ST_COUNT]
     // outputs
     int64_t *S1;        // [nbuckets * n]
     uint64_t *S2;       // [nbuckets * n * 2]
     uint64_t *hist;     // [hist_bins]
-    uint64_t *stats;    // [STAT_COUNT]
+    uint64_t *stats;    // [ST_COUNT]
     uint32_t *slot_nstar;  // [P] or null
     uint64_t *slot_units;  // [P] or null
     uint32_t *ctrl;     // [0]: next slot, [1]: error flags
@@ -56,7 +87,10 @@ enum ErrFlag { ERR_BUCKETS = 1 };
 
 // Launch the sampler (defined in mcpd_sampler.hip).  Returns a hipError_t
 // value as int.
-int launch_sampler(const RunArgs &a, int grid, int block, bool lds_state, int row_stride,
+int launch_sampler(const RunArgs &a, int grid, int block, bool lds_state, bool lds_tables,
                    void *stream);
+
+// Bytes of dynamic LDS a launch with this plan uses.
+size_t sampler_lds_bytes(const RunArgs &a, int block, bool lds_state, bool lds_tables);
 
 }  // namespace mcpd

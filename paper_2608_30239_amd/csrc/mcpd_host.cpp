@@ -22,7 +22,9 @@
 #include "mcpd_device.h"
 
 struct mcpd_instance {
-    int32_t n = 0, m = 0, dmax = 0, R = 4, gbits = 1;
+    int32_t n = 0, m = 0, dmax = 0, fmt = 0, gbits = 1;
+    uint32_t rec_bytes = 16, thr_len = 1;
+    std::vector<uint8_t> rows;   // row bytes of each record (record minus its first word)
     double fp = 0, fn = 0, q = 0;
     std::vector<int32_t> row_ptr, pool_idx;
     std::vector<uint8_t> y;
@@ -31,8 +33,7 @@ struct mcpd_instance {
     int device = 0;
     int cus = 0;
     // device tables
-    uint32_t *d_guide = nullptr, *d_cum = nullptr;
-    uint16_t *d_rows = nullptr;
+    uint32_t *d_guide = nullptr, *d_recs = nullptr;
     uint64_t *d_thr = nullptr;
     // workspace reused across runs
     int64_t *d_acc = nullptr;
@@ -40,9 +41,11 @@ struct mcpd_instance {
     uint32_t *d_lists = nullptr;
     uint32_t *d_gstate = nullptr;
     size_t gstate_words = 0;
+    uint64_t *d_lane_stats = nullptr;
+    size_t lane_stats_cap = 0;
     int64_t *d_S1 = nullptr;
     uint64_t *d_S2 = nullptr;
-    size_t bucket_cap = 0;
+    size_t bucket_cap = 0, bucket2_cap = 0;
     uint64_t *d_small = nullptr;   // hist + stats + ctrl
     size_t small_cap = 0;
     uint32_t *d_slot_nstar = nullptr;
@@ -73,6 +76,14 @@ int hip_fail(hipError_t e, const char *what)
     } while (0)
 
 constexpr uint32_t LIST_CAP = 64;
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS bytes of the table copy: thresholds, guide, clone records.
+size_t table_bytes(size_t thr_len, int gbits, size_t n, size_t rec_bytes)
+{
+    return align16(align16(align16(thr_len * 8) + ((size_t)4 << gbits)) + n * rec_bytes);
+}
 constexpr size_t LDS_BYTES = 160 * 1024;
 
 int validate_design(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx,
@@ -177,15 +188,20 @@ int upload(T **dptr, const std::vector<T> &h, hipStream_t s)
     return MCPD_OK;
 }
 
-// Site-draw tables from the masses.
+// Site-draw tables from the masses: clone records {inclusive cumulative
+// mass, pools} and the guide table.
 int upload_site_tables(mcpd_instance *I)
 {
     const int32_t n = I->n;
+    const size_t rw = I->rec_bytes / 4;
+    std::vector<uint32_t> recs((size_t)n * rw);
     std::vector<uint32_t> cum(n);
     uint64_t c = 0;
     for (int32_t i = 0; i < n; ++i) {
         c += I->mass[i];
         cum[i] = (uint32_t)(c - 1);
+        recs[(size_t)i * rw] = cum[i];
+        std::memcpy(&recs[(size_t)i * rw + 1], &I->rows[(size_t)i * (I->rec_bytes - 4)], I->rec_bytes - 4);
     }
     const uint32_t G = 1u << I->gbits;
     const uint32_t shift = 32u - (uint32_t)I->gbits;
@@ -196,7 +212,7 @@ int upload_site_tables(mcpd_instance *I)
         while ((uint64_t)cum[i] < lo) ++i;
         guide[b] = (uint32_t)i;
     }
-    int rc = upload(&I->d_cum, cum, I->stream);
+    int rc = upload(&I->d_recs, recs, I->stream);
     if (rc) return rc;
     return upload(&I->d_guide, guide, I->stream);
 }
@@ -208,7 +224,7 @@ void free_ptr(void *p)
 
 void release(mcpd_instance *I)
 {
-    free_ptr(I->d_guide); free_ptr(I->d_cum); free_ptr(I->d_rows); free_ptr(I->d_thr);
+    free_ptr(I->d_guide); free_ptr(I->d_recs); free_ptr(I->d_thr); free_ptr(I->d_lane_stats);
     free_ptr(I->d_acc); free_ptr(I->d_lists); free_ptr(I->d_gstate);
     free_ptr(I->d_S1); free_ptr(I->d_S2); free_ptr(I->d_small);
     free_ptr(I->d_slot_nstar); free_ptr(I->d_slot_units);
@@ -281,10 +297,32 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     mcpd_instance *I = new (std::nothrow) mcpd_instance();
     if (!I) return fail(MCPD_ENOMEM, "host allocation failed");
     I->n = n; I->m = m; I->dmax = dmax; I->fp = fp; I->fn = fn; I->q = q;
-    I->R = dmax <= 4 ? 4 : dmax <= 8 ? 8 : 16;
+    // record format: narrowest entries, shortest compile-time loop >= dmax
+    if (m <= 127) {
+        I->fmt = dmax <= 4 ? mcpd::FMT_U8_4 : dmax <= 5 ? mcpd::FMT_U8_5 : dmax <= 8 ? mcpd::FMT_U8_8 : mcpd::FMT_U8_12;
+    } else {
+        I->fmt = dmax <= 4 ? mcpd::FMT_U16_4 : dmax <= 8 ? mcpd::FMT_U16_8 : mcpd::FMT_U16_12;
+    }
+    I->rec_bytes = (uint32_t)mcpd::fmt_rec_bytes(I->fmt);
     int gb = 1;
     while ((1 << gb) < n) ++gb;
-    I->gbits = std::min(gb, 24);
+    gb = std::min(gb, 24);
+    {
+        // Halve the guide (at most twice) when that lets the chain state of
+        // 256 lanes and all tables share the LDS.
+        const size_t state = ((size_t)(n + 15) / 16 + (size_t)(m + 1) / 2) * 256 * 4 + 64 * 4;
+        const size_t thr_len = ((size_t)2 << dmax) - 1;
+        const int full = gb;
+        if (state + table_bytes(thr_len, full, n, I->rec_bytes) > LDS_BYTES) {
+            for (int cut = 1; cut <= 2 && full - cut >= 1; ++cut) {
+                if (state + table_bytes(thr_len, full - cut, n, I->rec_bytes) <= LDS_BYTES) {
+                    gb = full - cut;
+                    break;
+                }
+            }
+        }
+    }
+    I->gbits = gb;
     I->row_ptr.assign(row_ptr, row_ptr + n + 1);
     I->pool_idx.assign(pool_idx, pool_idx + row_ptr[n]);
     I->y.assign(y, y + m);
@@ -296,12 +334,22 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     rc = quantize(n, w.data(), I->mass);
     if (rc) { delete I; return rc; }
 
-    // rows
-    std::vector<uint16_t> rows((size_t)n * I->R, 0xFFFFu);
-    for (int32_t i = 0; i < n; ++i)
-        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
-            rows[(size_t)i * I->R + (e - row_ptr[i])] =
-                (uint16_t)(pool_idx[e] | ((uint32_t)y[pool_idx[e]] << 15));
+    // record payload: entry = pool | outcome << (top bit), ascending, padded with all-ones
+    const size_t pay = I->rec_bytes - 4;
+    I->rows.assign((size_t)n * pay, 0xFFu);
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const uint32_t j = (uint32_t)pool_idx[e], yj = y[pool_idx[e]];
+            const size_t at = (size_t)i * pay;
+            const int32_t pos = e - row_ptr[i];
+            if (!mcpd::fmt_wide(I->fmt)) {
+                I->rows[at + pos] = (uint8_t)(j | (yj << 7));
+            } else {
+                const uint16_t v = (uint16_t)(j | (yj << 15));
+                std::memcpy(&I->rows[at + 2 * pos], &v, 2);
+            }
+        }
+    }
 
     // thresholds for every ordered pattern of free-pool outcomes: the FP64
     // sum lq + a_{1st} + a_{2nd} + ... in ascending pool order
@@ -309,6 +357,7 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     const double a_pos = std::log(1.0 - fn) - std::log(fp);
     const double a_neg = std::log(fn) - std::log(1.0 - fp);
     std::vector<uint64_t> thr(((size_t)2 << dmax) - 1);
+    I->thr_len = (uint32_t)thr.size();
     for (int len = 0; len <= dmax; ++len) {
         for (uint32_t pat = 0; pat < (1u << len); ++pat) {
             double L = lq;
@@ -324,8 +373,7 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     if (e != hipSuccess) { delete I; return hip_fail(e, "hipGetDevice"); }
     e = hipDeviceGetAttribute(&I->cus, hipDeviceAttributeMultiprocessorCount, I->device);
     if (e != hipSuccess) { delete I; return hip_fail(e, "hipDeviceGetAttribute"); }
-    if ((rc = upload(&I->d_rows, rows, I->stream)) || (rc = upload(&I->d_thr, thr, I->stream)) ||
-        (rc = upload_site_tables(I))) {
+    if ((rc = upload(&I->d_thr, thr, I->stream)) || (rc = upload_site_tables(I))) {
         release(I);
         delete I;
         return rc;
@@ -396,11 +444,14 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
 
     mcpd::RunArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.T.guide = I->d_guide; a.T.cum_hi = I->d_cum; a.T.rows = I->d_rows; a.T.thr = I->d_thr;
-    a.T.n = n; a.T.m = I->m; a.T.dmax = I->dmax; a.T.R = I->R;
+    a.T.guide = I->d_guide; a.T.recs = I->d_recs; a.T.thr = I->d_thr;
+    a.T.n = n; a.T.m = I->m; a.T.dmax = I->dmax; a.T.fmt = I->fmt;
     a.T.gshift = 32u - (uint32_t)I->gbits;
+    a.T.gbits = (uint32_t)I->gbits;
+    a.T.rec_bytes = I->rec_bytes;
+    a.T.thr_len = I->thr_len;
     a.B = B;
-    a.capmax = opts.max_steps ? std::max<uint64_t>(opts.max_steps, m) : 0xFFFFFFFFull;
+    a.capmax = opts.max_steps ? (uint32_t)std::max<uint64_t>(opts.max_steps, m) : 0xFFFFFFFFu;
     a.seed = seed;
     a.P = slots;
     a.k = k; a.ell = m; a.W = m - k + 1; a.cmin = cmin;
@@ -414,27 +465,37 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
     a.list_cap = LIST_CAP;
     a.nbuckets = nbuckets;
 
-    // Launch plan: state in LDS with the widest workgroup that fits.
-    const size_t words = (size_t)a.words_bits + a.words_cnt;
-    const size_t hist_b = (size_t)opts.hist_bins * 4u;
+    // LDS copy of the read-only tables: thresholds, cumulative masses, guide, rows.
+    a.tab_off_thr = 0;
+    a.tab_off_guide = (uint32_t)align16((size_t)I->thr_len * 8);
+    a.tab_off_recs = (uint32_t)align16(a.tab_off_guide + ((size_t)4 << I->gbits));
+    const size_t tab_bytes = table_bytes(I->thr_len, I->gbits, n, I->rec_bytes);
+    a.tab_bytes = tab_bytes > LDS_BYTES ? 0u : (uint32_t)tab_bytes;
+
+    // Launch plan.  Chain state in LDS needs at least one full wave per SIMD
+    // (256 lanes per CU) to be worth it; otherwise the state goes to global
+    // memory and more waves hide its latency.  Tables go to LDS when they fit
+    // next to whatever else the workgroup keeps there.
     int block = 256;
-    bool lds_state = false;
-    for (int L : {256, 128, 64}) {
-        if (words * (size_t)L * 4u + hist_b <= LDS_BYTES) { block = L; lds_state = true; break; }
-    }
+    bool lds_state = false, lds_tables = false;
     size_t wg_per_cu = 1;
-    if (lds_state) {
-        wg_per_cu = LDS_BYTES / (words * (size_t)block * 4u + hist_b);
-        wg_per_cu = std::max<size_t>(1, std::min<size_t>(wg_per_cu, 2048 / block));
-    } else {
-        block = 256;
-        wg_per_cu = 4;
+    auto fits = [&](int L, bool sl, bool tl) {
+        if (tl && !a.tab_bytes) return false;
+        return mcpd::sampler_lds_bytes(a, L, sl, tl) <= LDS_BYTES;
+    };
+    if (fits(256, true, true)) { lds_state = lds_tables = true; }
+    else if (fits(256, true, false)) { lds_state = true; }
+    else { lds_tables = fits(256, false, true); }
+    {
+        const size_t per_wg = mcpd::sampler_lds_bytes(a, block, lds_state, lds_tables);
+        const size_t by_lds = per_wg ? LDS_BYTES / per_wg : 8;
+        const size_t by_waves = lds_state ? 2048 / block : 1024 / block;
+        wg_per_cu = std::max<size_t>(1, std::min(by_lds, by_waves));
     }
     const size_t max_lanes = (size_t)I->cus * wg_per_cu * (size_t)block;
     const size_t want_lanes = std::min<size_t>(((size_t)slots + block - 1) / block * block, max_lanes);
     const int grid = (int)(want_lanes / block);
     const size_t lanes = (size_t)grid * block;
-
     // Workspace.  Numerator rows are kept zero between runs by the kernel.
     int rc;
     if (I->acc_lanes < lanes || !I->d_acc) {
@@ -448,15 +509,12 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
         if ((rc = ensure(&I->d_lists, cap, lanes * LIST_CAP))) return rc;
         I->acc_lanes = lanes;
     }
+    const size_t words = (size_t)a.words_bits + a.words_cnt;
     if (!lds_state) {
         if ((rc = ensure(&I->d_gstate, I->gstate_words, lanes * words))) return rc;
     }
     if ((rc = ensure(&I->d_S1, I->bucket_cap, (size_t)nbuckets * n))) return rc;
-    {
-        size_t cap2 = 0;
-        free_ptr(I->d_S2); I->d_S2 = nullptr;
-        if ((rc = ensure(&I->d_S2, cap2, (size_t)nbuckets * n * 2))) return rc;
-    }
+    if ((rc = ensure(&I->d_S2, I->bucket2_cap, (size_t)nbuckets * n * 2))) return rc;
     const size_t small_words = opts.hist_bins + mcpd::ST_COUNT + 2;
     if ((rc = ensure(&I->d_small, I->small_cap, small_words))) return rc;
     if (opts.slot_nstar || opts.slot_units) {
@@ -471,6 +529,8 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
             I->slot_cap = slots;
         }
     }
+    if ((rc = ensure(&I->d_lane_stats, I->lane_stats_cap, lanes * mcpd::ST_COUNT))) return rc;
+    a.lane_stats = I->d_lane_stats;
     a.acc = I->d_acc;
     a.lists = I->d_lists;
     a.gstate = lds_state ? nullptr : I->d_gstate;
@@ -487,7 +547,7 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
     HIP_TRY(hipMemsetAsync(I->d_small, 0, small_words * sizeof(uint64_t), I->stream));
 
     HIP_TRY(hipEventRecord(I->ev0, I->stream));
-    int e = mcpd::launch_sampler(a, grid, block, lds_state, I->R, I->stream);
+    int e = mcpd::launch_sampler(a, grid, block, lds_state, lds_tables, I->stream);
     if (e != hipSuccess) return hip_fail((hipError_t)e, "sampler launch");
     HIP_TRY(hipEventRecord(I->ev1, I->stream));
 
@@ -560,7 +620,7 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
         stats->rollback_units = st[mcpd::ST_ROLLBACK_UNITS];
         stats->kernel_ms = ms;
         stats->lanes = (uint64_t)lanes;
-        stats->lds_state = lds_state ? 1u : 0u;
+        stats->lds_state = (lds_state ? 1u : 0u) | (lds_tables ? 2u : 0u);
     }
     if (opts.strict_cap && st[mcpd::ST_CAP_HITS]) return fail(MCPD_ECAP, "a retained pair hit the meeting cap");
     return MCPD_OK;

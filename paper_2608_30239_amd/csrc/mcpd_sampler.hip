@@ -16,7 +16,14 @@
 // laid out structure-of-arrays with the lane index fastest, so that the 64
 // lanes of a wave touching any word index hit 64 distinct banks.  The state
 // lives in LDS when the instance fits, otherwise in global memory with the
-// same layout.
+// same layout.  The read-only instance tables (thresholds, guide table and
+// clone records holding the cumulative mass and the pools of each clone) are
+// copied into LDS when they fit, so that a draw touches no global memory.
+//
+// A draw is a short chain of LDS round trips: guide -> clone record (site
+// and pools in one read) -> all count words of the clone at once -> the
+// threshold of the free-pool pattern.  Control flow inside a draw is
+// branch-free except for the rare flip, event and bookkeeping paths.
 //
 // Estimator: the numerator V_j = W H_{k:l}(h_j) (Section "Coupled Estimator
 // and Fixed-Budget GPU Execution") is accumulated exactly in 64-bit integers
@@ -26,11 +33,13 @@
 //       - sum_{changes c of Delta_j at time s} c G(s-1)
 //       (+ G(C) Delta_j(C) for a pair stopped by the cap),
 // using sum_s c = Delta_j(C) (= 0 once the pair has met, Theorem 1 (d)).
-// A draw at t changes Delta at time t+1 by dx - dy.  Numerators go to a
-// per-lane row of int64 with no-return atomics; a replication that can no
-// longer be retained (it would complete beyond B) is stopped and rolled back
-// by replaying its draws with negated contributions.  At the end of a slot
-// its numerators are added to integer buckets keyed by N*_p, which makes the
+// A draw at t changes Delta at time t+1 by dx - dy.  Each lane keeps the
+// numerators of up to CACHE clones of its slot in registers and spills any
+// further clone to its own int64 row in global memory (no-return atomics,
+// recorded in a touched list).  A replication that can no longer be retained
+// (it would complete beyond B) is stopped and rolled back by replaying its
+// draws with negated contributions.  At the end of a slot its numerators are
+// added to integer buckets keyed by N*_p, which makes the
 // completion-time-corrected aggregate exact and order-independent.
 #include <hip/hip_runtime.h>
 
@@ -44,6 +53,7 @@ constexpr uint32_t MODE_NEED_REP = 1;
 constexpr uint32_t MODE_RUN = 2;
 constexpr uint32_t MODE_DONE = 3;
 constexpr uint32_t NO_TAG = 0xFFFFFFFFu;
+constexpr int CACHE = 8;
 
 // Philox4x32-10 (Salmon et al., SC'11).  The key is wave-uniform, so its
 // schedule stays on the scalar unit.
@@ -77,56 +87,72 @@ __device__ __forceinline__ uint64_t gsum(uint32_t t, uint32_t k, uint32_t ell, u
 }
 
 struct Lane {
-    uint32_t mode, p, r, t, nret, tau, target;
+    uint32_t mode, p, r, t, nret, tau, target, lim;
     int32_t mu, sgn;
     uint64_t S;
     uint32_t lc, f0, f1;
-    uint64_t st[ST_COUNT];
+    uint32_t ctag[CACHE];
+    uint64_t cval[CACHE];
 };
 
-template <int R>
-struct RowWords { uint32_t w[R / 2]; };
+template <int F>
+struct Rec {
+    static constexpr int NE = fmt_entries(F);
+    static constexpr bool WIDE = fmt_wide(F);
+    static constexpr int WORDS = fmt_rec_bytes(F) / 4;
+    uint32_t w[WORDS];
 
-template <int R>
-__device__ __forceinline__ RowWords<R> load_row(const uint16_t *rows, uint32_t I)
-{
-    RowWords<R> rw;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(rows + (size_t)I * R);
-    if constexpr (R == 4) {
-        const uint2 v = *reinterpret_cast<const uint2 *>(src);
-        rw.w[0] = v.x; rw.w[1] = v.y;
-    } else if constexpr (R == 8) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(src);
-        rw.w[0] = v.x; rw.w[1] = v.y; rw.w[2] = v.z; rw.w[3] = v.w;
-    } else {
-        const uint4 v = *reinterpret_cast<const uint4 *>(src);
-        const uint4 u = *reinterpret_cast<const uint4 *>(src + 4);
-        rw.w[0] = v.x; rw.w[1] = v.y; rw.w[2] = v.z; rw.w[3] = v.w;
-        rw.w[4] = u.x; rw.w[5] = u.y; rw.w[6] = u.z; rw.w[7] = u.w;
+    __device__ __forceinline__ void load(const uint32_t *base, uint32_t I)
+    {
+        const uint32_t *src = base + (size_t)I * WORDS;
+        if constexpr (WORDS == 2) {
+            const uint2 v = *reinterpret_cast<const uint2 *>(src);
+            w[0] = v.x; w[1] = v.y;
+        } else if constexpr (WORDS == 4) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(src);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else {
+            const uint4 v = *reinterpret_cast<const uint4 *>(src);
+            const uint4 u = *reinterpret_cast<const uint4 *>(src + 4);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+            w[4] = u.x; w[5] = u.y; w[6] = u.z; w[7] = u.w;
+        }
     }
-    return rw;
-}
+    __device__ __forceinline__ uint32_t cum() const { return w[0]; }
+    __device__ __forceinline__ uint32_t raw(int e) const
+    {
+        if constexpr (WIDE) return (w[1 + (e >> 1)] >> ((e & 1) * 16)) & 0xFFFFu;
+        else return (w[1 + (e >> 2)] >> ((e & 3) * 8)) & 0xFFu;
+    }
+    __device__ __forceinline__ static bool valid(uint32_t v) { return WIDE ? v != 0xFFFFu : v != 0xFFu; }
+    __device__ __forceinline__ static uint32_t pool(uint32_t v) { return WIDE ? (v & 0x7FFFu) : (v & 0x7Fu); }
+    __device__ __forceinline__ static uint32_t outcome(uint32_t v) { return WIDE ? (v >> 15) : (v >> 7); }
+};
 
-template <int R>
-__device__ __forceinline__ uint32_t row_entry(const RowWords<R> &rw, int e)
-{
-    return (rw.w[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu;
-}
-
-template <bool LDS, int R>
+template <bool SL, bool TL, int F>
 struct Sampler {
     const RunArgs &a;
-    uint32_t *st;      // this workgroup's state base (LDS or global)
-    uint32_t L;        // lanes per workgroup (state stride)
-    uint32_t lane;     // lane within the workgroup
-    int64_t *acc;      // this lane's numerator row
-    uint32_t *list;    // this lane's touched list
+    uint32_t *st;           // this workgroup's state base (LDS or global)
+    const uint64_t *thr;    // tables (LDS copies or global)
+    const uint32_t *guide;
+    const uint32_t *recs;
+    uint32_t L;             // lanes per workgroup (state stride)
+    uint32_t lane;          // lane within the workgroup
+    int64_t *acc;           // this lane's spill row
+    uint32_t *list;         // this lane's touched list
+    uint64_t *ls;           // this lane's statistics
     uint32_t *hist_lds;
 
     __device__ __forceinline__ uint32_t &bits(uint32_t w) const { return st[w * L + lane]; }
-    __device__ __forceinline__ uint32_t &cnt(uint32_t q) const
+    __device__ __forceinline__ uint32_t &cnt(uint32_t q) const { return st[(a.words_bits + q) * L + lane]; }
+
+    __device__ __forceinline__ void stat_add(int i, uint64_t v) const
     {
-        return st[(a.words_bits + q) * L + lane];
+        atomicAdd(reinterpret_cast<unsigned long long *>(ls + i), (unsigned long long)v);
+    }
+    __device__ __forceinline__ void stat_max(int i, uint64_t v) const
+    {
+        atomicMax(reinterpret_cast<unsigned long long *>(ls + i), (unsigned long long)v);
     }
 
     __device__ void reset_state() const
@@ -135,7 +161,20 @@ struct Sampler {
         for (uint32_t w = 0; w < nw; ++w) st[w * L + lane] = 0u;
     }
 
-    __device__ __forceinline__ void event(Lane &s, uint32_t j, uint64_t v) const
+    // First draw count at which after_step has anything to decide: the end of
+    // the window, the cap, the end of a replay, or the abort point.
+    __device__ __forceinline__ void set_limit(Lane &s) const
+    {
+        uint32_t lim = a.ell < a.capmax ? a.ell : a.capmax;
+        if (s.sgn < 0 && s.target < lim) lim = s.target;
+        if (s.r >= 2u) {
+            const uint64_t ab = a.B - s.S + 1u;
+            if (ab < (uint64_t)lim) lim = (uint32_t)ab;
+        }
+        s.lim = lim;
+    }
+
+    __device__ __forceinline__ void spill(Lane &s, uint32_t j, uint64_t v) const
     {
         atomicAdd(reinterpret_cast<unsigned long long *>(acc + j), (unsigned long long)v);
         if (j != s.f0 && j != s.f1) {
@@ -143,6 +182,32 @@ struct Sampler {
             s.lc += 1;
             s.f1 = s.f0;
             s.f0 = j;
+        }
+    }
+
+    // Add v to clone j's numerator.  A clone holds a register entry for the
+    // rest of the slot once it has one; entries are never evicted, so a
+    // clone is either cached or spilled, never both.
+    __device__ __forceinline__ void event(Lane &s, uint32_t j, uint64_t v) const
+    {
+        bool hit = false;
+#pragma unroll
+        for (int e = 0; e < CACHE; ++e) {
+            const bool m = s.ctag[e] == j;
+            s.cval[e] += m ? v : 0ull;
+            hit |= m;
+        }
+        if (!hit) {
+            bool placed = false;
+#pragma unroll
+            for (int e = 0; e < CACHE; ++e) {
+                if (!placed && s.ctag[e] == NO_TAG) {
+                    s.ctag[e] = j;
+                    s.cval[e] = v;
+                    placed = true;
+                }
+            }
+            if (!placed) spill(s, j, v);
         }
     }
 
@@ -155,79 +220,98 @@ struct Sampler {
         return v >> (11u + a.ubits);
     }
 
-    // 1{U53 <= T}, U53 = (hw >> (32-b)) << (53-b) | low.
+    // 1{U53 <= T}, U53 = (hw >> (32-b)) << (53-b) | low; both high parts
+    // have b bits, so they compare as 32-bit words.
     __device__ __forceinline__ uint32_t decide(const Lane &s, uint32_t t, uint32_t hw, uint64_t T,
                                                bool &have_lo, uint64_t &lo) const
     {
         const uint32_t b = a.ubits;
-        const uint64_t hb = (uint64_t)(hw >> (32u - b));
-        const uint64_t th = T >> (53u - b);
+        const uint32_t hb = hw >> (32u - b);
+        const uint32_t th = (uint32_t)(T >> (53u - b));
         if (hb != th) return hb < th ? 1u : 0u;
         if (!have_lo) { lo = low_bits(s, t); have_lo = true; }
         return lo <= (T & ((1ull << (53u - b)) - 1ull)) ? 1u : 0u;
     }
 
     // One draw t of the current replication with site word sw and U word hw.
-    __device__ void step(Lane &s, uint32_t sw, uint32_t hw) const
+    __device__ __forceinline__ void step(Lane &s, uint32_t sw, uint32_t hw) const
     {
-        const DevTables &T = a.T;
+        using R = Rec<F>;
         const uint32_t t = s.t;
-        uint32_t I = T.guide[sw >> T.gshift];
-        while (T.cum_hi[I] < sw) ++I;
-        const RowWords<R> rw = load_row<R>(T.rows, I);
+        uint32_t I = guide[sw >> a.T.gshift];
+        R rc;
+        rc.load(recs, I);
+        while (rc.cum() < sw) {
+            ++I;
+            rc.load(recs, I);
+        }
+        // all state words of the draw, issued back to back
         const uint32_t bw_idx = I >> 4;
         const uint32_t bw = bits(bw_idx);
+        uint32_t cw[R::NE];
+#pragma unroll
+        for (int e = 0; e < R::NE; ++e) {
+            const uint32_t v = rc.raw(e);
+            cw[e] = cnt((R::valid(v) ? R::pool(v) : 0u) >> 1);
+        }
         const uint32_t sh = (I & 15u) << 1;
         const uint32_t xi = (bw >> sh) & 1u;
         const uint32_t yi = (bw >> (sh + 1u)) & 1u;
         const bool updY = (s.tau == 0u) && (t > 0u);
 
-        uint32_t patX = 0, lenX = 0, patY = 0, lenY = 0;
+        uint32_t patX = 0, lenX = 0;
 #pragma unroll
-        for (int e = 0; e < R; ++e) {
-            const uint32_t v = row_entry<R>(rw, e);
-            if (v == 0xFFFFu) continue;
-            const uint32_t j = v & 0x7FFFu, yj = v >> 15;
-            const uint32_t cw = cnt(j >> 1);
-            const uint32_t cs = (j & 1u) << 4;
-            const uint32_t cx = (cw >> cs) & 0xFFu;
-            const uint32_t cy = (cw >> (cs + 8u)) & 0xFFu;
-            if (cx == xi) { patX = (patX << 1) | yj; ++lenX; }
-            if (cy == yi) { patY = (patY << 1) | yj; ++lenY; }
+        for (int e = 0; e < R::NE; ++e) {
+            const uint32_t v = rc.raw(e);
+            const uint32_t cs = (R::pool(v) & 1u) << 4;
+            const bool f = R::valid(v) && ((cw[e] >> cs) & 0xFFu) == xi;
+            patX = f ? ((patX << 1) | R::outcome(v)) : patX;
+            lenX += f ? 1u : 0u;
         }
         bool have_lo = false;
         uint64_t lo = 0;
-        const uint32_t xn = decide(s, t, hw, T.thr[(1u << lenX) - 1u + patX], have_lo, lo);
+        const uint32_t xn = decide(s, t, hw, thr[(1u << lenX) - 1u + patX], have_lo, lo);
         uint32_t yn = yi;
-        if (updY) yn = decide(s, t, hw, T.thr[(1u << lenY) - 1u + patY], have_lo, lo);
+        if (updY) {
+            uint32_t patY = 0, lenY = 0;
+#pragma unroll
+            for (int e = 0; e < R::NE; ++e) {
+                const uint32_t v = rc.raw(e);
+                const uint32_t cs = ((R::pool(v) & 1u) << 4) + 8u;
+                const bool f = R::valid(v) && ((cw[e] >> cs) & 0xFFu) == yi;
+                patY = f ? ((patY << 1) | R::outcome(v)) : patY;
+                lenY += f ? 1u : 0u;
+            }
+            yn = decide(s, t, hw, thr[(1u << lenY) - 1u + patY], have_lo, lo);
+        }
         const int dx = (int)xn - (int)xi;
         const int dy = (int)yn - (int)yi;
         if (dx | dy) {
             bits(bw_idx) = bw ^ ((uint32_t)(dx != 0) << sh) ^ ((uint32_t)(dy != 0) << (sh + 1u));
 #pragma unroll
-            for (int e = 0; e < R; ++e) {
-                const uint32_t v = row_entry<R>(rw, e);
-                if (v == 0xFFFFu) continue;
-                const uint32_t j = v & 0x7FFFu;
+            for (int e = 0; e < R::NE; ++e) {
+                const uint32_t v = rc.raw(e);
+                if (!R::valid(v)) continue;
+                const uint32_t j = R::pool(v);
                 const uint32_t cs = (j & 1u) << 4;
                 const uint32_t delta = ((uint32_t)dx << cs) + ((uint32_t)dy << (cs + 8u));
-                cnt(j >> 1) += delta;
+                if constexpr (SL) atomicAdd(&cnt(j >> 1), delta);   // LDS, no return
+                else cnt(j >> 1) += delta;
             }
+            if (s.tau == 0u) s.mu += (int)(xn != yn) - (int)(xi != yi);
+            // estimator events at time te = t + 1
+            uint64_t val = 0;
+            const uint32_t te = t + 1u;
+            if (dx != 0 && te <= a.ell) {
+                const uint32_t from = te > a.k ? te : a.k;
+                val += (uint64_t)(int64_t)dx * (uint64_t)(a.ell - from + 1u);
+            }
+            if (updY && t >= a.k + 1u && dx != dy)
+                val -= (uint64_t)(int64_t)(dx - dy) * gsum(t, a.k, a.ell, a.W);
+            if (val != 0) event(s, I, s.sgn > 0 ? val : (uint64_t)0 - val);
         }
-        if (s.tau == 0u) s.mu += (int)(xn != yn) - (int)(xi != yi);
-        // estimator events at time te = t + 1
-        uint64_t val = 0;
-        const uint32_t te = t + 1u;
-        if (dx != 0 && te <= a.ell) {
-            const uint32_t from = te > a.k ? te : a.k;
-            val += (uint64_t)(int64_t)dx * (uint64_t)(a.ell - from + 1u);
-        }
-        if (updY && t >= a.k + 1u && dx != dy) {
-            val -= (uint64_t)(int64_t)(dx - dy) * gsum(t, a.k, a.ell, a.W);
-        }
-        if (val != 0) event(s, I, s.sgn > 0 ? val : (uint64_t)0 - val);
-        if (s.tau == 0u && s.mu == 0) s.tau = te;
-        s.t = te;
+        if (s.tau == 0u && s.mu == 0) s.tau = t + 1u;
+        s.t = t + 1u;
     }
 
     // Boundary term G(C) Delta_j(C) of a pair stopped by the cap.
@@ -271,38 +355,48 @@ struct Sampler {
     __device__ void flush_slot(Lane &s) const
     {
         const uint32_t nstar = s.nret;
-        if (s.lc <= a.list_cap) {
-            for (uint32_t e = 0; e < s.lc; ++e) {
-                const uint32_t j = __hip_atomic_load(list + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int64_t v = (int64_t)atomicExch(reinterpret_cast<unsigned long long *>(acc + j), 0ull);
-                if (v != 0) emit(nstar, j, v);
-            }
-        } else {
-            for (uint32_t j = 0; j < (uint32_t)a.T.n; ++j) {
-                const int64_t v = (int64_t)atomicExch(reinterpret_cast<unsigned long long *>(acc + j), 0ull);
-                if (v != 0) emit(nstar, j, v);
+#pragma unroll
+        for (int e = 0; e < CACHE; ++e) {
+            if (s.ctag[e] != NO_TAG && s.cval[e] != 0) emit(nstar, s.ctag[e], (int64_t)s.cval[e]);
+            s.ctag[e] = NO_TAG;
+            s.cval[e] = 0;
+        }
+        if (s.lc > 0) {
+            if (s.lc <= a.list_cap) {
+                for (uint32_t e = 0; e < s.lc; ++e) {
+                    const uint32_t j = __hip_atomic_load(list + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int64_t v = (int64_t)atomicExch(reinterpret_cast<unsigned long long *>(acc + j), 0ull);
+                    if (v != 0) emit(nstar, j, v);
+                }
+            } else {
+                for (uint32_t j = 0; j < (uint32_t)a.T.n; ++j) {
+                    const int64_t v = (int64_t)atomicExch(reinterpret_cast<unsigned long long *>(acc + j), 0ull);
+                    if (v != 0) emit(nstar, j, v);
+                }
             }
         }
         if (a.slot_nstar) a.slot_nstar[s.p] = nstar;
         if (a.slot_units) a.slot_units[s.p] = s.S;
-        if (nstar > s.st[ST_NSTAR_MAX]) s.st[ST_NSTAR_MAX] = nstar;
+        stat_max(ST_NSTAR_MAX, nstar);
         s.mode = MODE_NEED_SLOT;
     }
 
     __device__ void begin_rollback(Lane &s, uint32_t draws) const
     {
-        s.st[ST_REPS_ABORTED] += 1;
-        s.st[ST_ROLLBACK_UNITS] += draws;
+        stat_add(ST_REPS_ABORTED, 1);
+        stat_add(ST_ROLLBACK_UNITS, draws);
+        stat_add(ST_PROGRESS, 2ull * draws);
         s.target = draws;
         s.sgn = -1;
         s.mode = MODE_NEED_REP;
     }
 
-    // Bookkeeping after a draw: completion, retention, abort, end of replay.
+    // Bookkeeping once the draw count reaches the lane's limit: completion,
+    // retention, abort, end of replay.
     __device__ void after_step(Lane &s) const
     {
         const uint32_t d = s.t;
-        const bool capped = (s.tau == 0u) && ((uint64_t)d >= a.capmax);
+        const bool capped = (s.tau == 0u) && (d >= a.capmax);
         const bool ended = capped || (s.tau != 0u && d >= a.ell);
         if (s.sgn < 0) {
             if (d == s.target) {
@@ -318,21 +412,22 @@ struct Sampler {
             if (!retained) { begin_rollback(s, d); return; }
             s.S += C;
             s.nret += 1u;
-            s.st[ST_RETAINED_UNITS] += C;
-            s.st[ST_REPS_RETAINED] += 1;
+            stat_add(ST_RETAINED_UNITS, C);
+            stat_add(ST_PROGRESS, C);
+            stat_add(ST_REPS_RETAINED, 1);
             if (capped) {
-                s.st[ST_CAP_HITS] += 1;
-                s.st[ST_SINGLE_SITE] += 1 + 2 * (C - 1);
+                stat_add(ST_CAP_HITS, 1);
+                stat_add(ST_SINGLE_SITE, 1 + 2 * (C - 1));
             } else {
                 const uint64_t mt = s.tau < d ? s.tau : d;
-                s.st[ST_SINGLE_SITE] += 1 + 2 * (mt - 1) + (C - mt);
-                s.st[ST_TAU_SUM] += s.tau;
-                if (s.tau > s.st[ST_TAU_MAX]) s.st[ST_TAU_MAX] = s.tau;
+                stat_add(ST_SINGLE_SITE, 1 + 2 * (mt - 1) + (C - mt));
+                stat_add(ST_TAU_SUM, s.tau);
+                stat_max(ST_TAU_MAX, s.tau);
                 uint32_t bin = s.tau / a.hist_width;
                 if (bin >= a.hist_bins) bin = a.hist_bins - 1u;
                 atomicAdd(hist_lds + bin, 1u);
             }
-            if (s.r == 1u && C > a.B) s.st[ST_ZERO_COMPLETION] += 1;
+            if (s.r == 1u && C > a.B) stat_add(ST_ZERO_COMPLETION, 1);
             if (!a.refill || s.S >= a.B || s.S + a.cmin > a.B) flush_slot(s);
             else s.mode = MODE_NEED_REP;
             return;
@@ -341,81 +436,106 @@ struct Sampler {
     }
 };
 
-template <bool LDS, int R>
+// Copy n32 dwords from global memory into LDS, all threads of the block.
+__device__ __forceinline__ void copy_to_lds(uint32_t *dst, const void *src, uint32_t n32)
+{
+    const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
+    for (uint32_t i = threadIdx.x; i < n32; i += blockDim.x) dst[i] = s[i];
+}
+
+template <bool SL, bool TL, int F>
 __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
 {
     extern __shared__ uint32_t smem[];
     const uint32_t L = blockDim.x;
     const uint32_t lane = threadIdx.x;
     const uint32_t words = a.words_bits + a.words_cnt;
-    uint32_t *hist_lds = LDS ? smem + (size_t)words * L : smem;
+    uint32_t *after_state = SL ? smem + (size_t)words * L : smem;
+    uint32_t *hist_lds = after_state;
+    uint32_t *tab = after_state + ((a.hist_bins + 3u) & ~3u);   // keeps 16-byte alignment
     for (uint32_t b = lane; b < a.hist_bins; b += L) hist_lds[b] = 0u;
+    if (TL) {
+        copy_to_lds(tab + a.tab_off_thr / 4, a.T.thr, a.T.thr_len * 2u);
+        copy_to_lds(tab + a.tab_off_guide / 4, a.T.guide, 1u << a.T.gbits);
+        copy_to_lds(tab + a.tab_off_recs / 4, a.T.recs, (uint32_t)a.T.n * a.T.rec_bytes / 4u);
+    }
+    const size_t gl = (size_t)blockIdx.x * L + lane;
+    uint64_t *ls = a.lane_stats + gl * ST_COUNT;
+#pragma unroll
+    for (int i = 0; i < ST_COUNT; ++i) ls[i] = 0;
     __syncthreads();
 
-    const size_t gl = (size_t)blockIdx.x * L + lane;
-    Sampler<LDS, R> S{a,
-                      LDS ? smem : a.gstate + (size_t)blockIdx.x * words * L,
-                      L,
-                      lane,
-                      a.acc + gl * (size_t)a.T.n,
-                      a.lists + gl * (size_t)a.list_cap,
-                      hist_lds};
+    Sampler<SL, TL, F> S{a,
+                         SL ? smem : a.gstate + (size_t)blockIdx.x * words * L,
+                         TL ? reinterpret_cast<const uint64_t *>(tab + a.tab_off_thr / 4) : a.T.thr,
+                         TL ? tab + a.tab_off_guide / 4 : a.T.guide,
+                         TL ? tab + a.tab_off_recs / 4 : a.T.recs,
+                         L,
+                         lane,
+                         a.acc + gl * (size_t)a.T.n,
+                         a.lists + gl * (size_t)a.list_cap,
+                         ls,
+                         hist_lds};
     Lane s;
     s.mode = MODE_NEED_SLOT;
-    s.p = s.r = s.t = s.nret = s.tau = s.target = 0;
+    s.p = s.r = s.t = s.nret = s.tau = s.target = s.lim = 0;
     s.mu = 0;
     s.sgn = 1;
     s.S = 0;
     s.lc = 0;
     s.f0 = s.f1 = NO_TAG;
-    for (int i = 0; i < ST_COUNT; ++i) s.st[i] = 0;
+#pragma unroll
+    for (int e = 0; e < CACHE; ++e) { s.ctag[e] = NO_TAG; s.cval[e] = 0; }
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
 
     for (;;) {
-        if (s.mode == MODE_NEED_SLOT) {
-            const uint32_t p = atomicAdd(&a.ctrl[0], 1u);
-            if (p >= a.P) {
-                s.mode = MODE_DONE;
-            } else {
-                s.p = p;
-                s.r = 0;
-                s.S = 0;
-                s.nret = 0;
-                s.lc = 0;
-                s.f0 = s.f1 = NO_TAG;
-                s.sgn = 1;
-                s.mode = MODE_NEED_REP;
+        if (s.mode != MODE_RUN) {
+            if (s.mode == MODE_NEED_SLOT) {
+                const uint32_t p = atomicAdd(&a.ctrl[0], 1u);
+                if (p >= a.P) {
+                    s.mode = MODE_DONE;
+                } else {
+                    s.p = p;
+                    s.r = 0;
+                    s.S = 0;
+                    s.nret = 0;
+                    s.lc = 0;
+                    s.f0 = s.f1 = NO_TAG;
+                    s.sgn = 1;
+                    s.mode = MODE_NEED_REP;
+                }
             }
-        }
-        if (s.mode == MODE_NEED_REP) {
-            if (s.sgn > 0) {
-                s.r += 1u;
-                s.st[ST_REPS_STARTED] += 1;
+            if (s.mode == MODE_NEED_REP) {
+                if (s.sgn > 0) {
+                    s.r += 1u;
+                    S.stat_add(ST_REPS_STARTED, 1);
+                }
+                S.reset_state();
+                s.t = 0;
+                s.tau = 0;
+                s.mu = 0;
+                S.set_limit(s);
+                s.mode = MODE_RUN;
             }
-            S.reset_state();
-            s.t = 0;
-            s.tau = 0;
-            s.mu = 0;
-            s.mode = MODE_RUN;
         }
         if (__all(s.mode == MODE_DONE)) break;
         if (s.mode == MODE_RUN) {
             uint32_t w[4];
             philox10(s.t >> 1, s.r, s.p, a.g, k0, k1, w);
             S.step(s, w[0], w[1]);
-            s.st[ST_PROGRESS] += 1;
-            S.after_step(s);
+            if (s.t >= s.lim) S.after_step(s);
             if (s.mode == MODE_RUN) {
                 S.step(s, w[2], w[3]);
-                s.st[ST_PROGRESS] += 1;
-                S.after_step(s);
+                if (s.t >= s.lim) S.after_step(s);
             }
         }
     }
 
-    // Statistics: wave reduction, then one atomic per wave.
+    // Statistics: each lane reads back its own slots, wave reduction, then
+    // one atomic per wave.
+#pragma unroll
     for (int i = 0; i < ST_COUNT; ++i) {
-        uint64_t v = s.st[i];
+        uint64_t v = __hip_atomic_load(ls + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const bool is_max = (i == ST_TAU_MAX || i == ST_NSTAR_MAX);
         for (int off = 32; off > 0; off >>= 1) {
             const uint64_t o = __shfl_xor(v, off);
@@ -431,37 +551,52 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
         if (hist_lds[b]) atomicAdd(reinterpret_cast<unsigned long long *>(a.hist + b), (unsigned long long)hist_lds[b]);
 }
 
-template <bool LDS>
-int launch_R(const RunArgs &a, int grid, int block, int R, size_t lds, hipStream_t st)
+template <bool SL, bool TL, int F>
+int launch_one(const RunArgs &a, int grid, int block, size_t lds, hipStream_t st)
 {
-    switch (R) {
-    case 4: hipLaunchKernelGGL((sampler_kernel<LDS, 4>), dim3(grid), dim3(block), lds, st, a); break;
-    case 8: hipLaunchKernelGGL((sampler_kernel<LDS, 8>), dim3(grid), dim3(block), lds, st, a); break;
-    case 16: hipLaunchKernelGGL((sampler_kernel<LDS, 16>), dim3(grid), dim3(block), lds, st, a); break;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(sampler_kernel<SL, TL, F>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return (int)e;
+    }
+    hipLaunchKernelGGL((sampler_kernel<SL, TL, F>), dim3(grid), dim3(block), lds, st, a);
+    return (int)hipGetLastError();
+}
+
+template <bool SL, bool TL>
+int launch_fmt(const RunArgs &a, int grid, int block, size_t lds, hipStream_t st)
+{
+    switch (a.T.fmt) {
+    case FMT_U8_4: return launch_one<SL, TL, FMT_U8_4>(a, grid, block, lds, st);
+    case FMT_U8_5: return launch_one<SL, TL, FMT_U8_5>(a, grid, block, lds, st);
+    case FMT_U8_8: return launch_one<SL, TL, FMT_U8_8>(a, grid, block, lds, st);
+    case FMT_U8_12: return launch_one<SL, TL, FMT_U8_12>(a, grid, block, lds, st);
+    case FMT_U16_4: return launch_one<SL, TL, FMT_U16_4>(a, grid, block, lds, st);
+    case FMT_U16_8: return launch_one<SL, TL, FMT_U16_8>(a, grid, block, lds, st);
+    case FMT_U16_12: return launch_one<SL, TL, FMT_U16_12>(a, grid, block, lds, st);
     default: return (int)hipErrorInvalidValue;
     }
-    return (int)hipGetLastError();
 }
 
 }  // namespace
 
-int launch_sampler(const RunArgs &a, int grid, int block, bool lds_state, int row_stride, void *stream)
+size_t sampler_lds_bytes(const RunArgs &a, int block, bool lds_state, bool lds_tables)
 {
     const size_t words = (size_t)a.words_bits + a.words_cnt;
-    const size_t lds = (lds_state ? words * (size_t)block * 4u : 0u) + (size_t)a.hist_bins * 4u;
+    return (lds_state ? words * (size_t)block * 4u : 0u) + (size_t)((a.hist_bins + 3u) & ~3u) * 4u +
+           (lds_tables ? (size_t)a.tab_bytes : 0u);
+}
+
+int launch_sampler(const RunArgs &a, int grid, int block, bool lds_state, bool lds_tables, void *stream)
+{
+    const size_t lds = sampler_lds_bytes(a, block, lds_state, lds_tables);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (lds_state) {
-        if (lds > 64 * 1024) {
-            hipError_t e = hipFuncSetAttribute(
-                reinterpret_cast<const void *>(row_stride == 4 ? sampler_kernel<true, 4>
-                                               : row_stride == 8 ? sampler_kernel<true, 8>
-                                                                 : sampler_kernel<true, 16>),
-                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return (int)e;
-        }
-        return launch_R<true>(a, grid, block, row_stride, lds, st);
+        return lds_tables ? launch_fmt<true, true>(a, grid, block, lds, st)
+                          : launch_fmt<true, false>(a, grid, block, lds, st);
     }
-    return launch_R<false>(a, grid, block, row_stride, lds, st);
+    return lds_tables ? launch_fmt<false, true>(a, grid, block, lds, st)
+                      : launch_fmt<false, false>(a, grid, block, lds, st);
 }
 
 }  // namespace mcpd

@@ -139,6 +139,19 @@ def test_global_state_path():
     assert gpu["stats"]["lds_state"] == 0
 
 
+def test_lds_state_global_tables():
+    # state fills LDS at 256 lanes, the tables no longer fit beside it
+    inst = I.make_instance("lds_state_only", 1600, 110, 5, 3, 0.05, 0.1, prior=3 / 1600, seed=4)
+    gpu, _ = compare(inst, 2048 * 2000, 2048, 60, 600, seed=2)
+    assert gpu["stats"]["lds_state"] == 1
+
+
+def test_global_state_lds_tables():
+    inst = I.make_instance("lds_tables_only", 3000, 400, (3, 7), 5, 0.1, 0.05, prior=5 / 3000, seed=5)
+    gpu, _ = compare(inst, 1024 * 1500, 1024, 30, 500, seed=3)
+    assert gpu["stats"]["lds_state"] == 2
+
+
 def test_deterministic_repeat():
     inst, rp = I.tiny_plain()
     dec = N.Decoder(inst)
@@ -171,5 +184,5 @@ def test_invalid_arguments_raise():
 def test_paper_shaped_full_size():
     inst, rp = I.paper_shaped()
     gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed)
-    assert gpu["stats"]["lds_state"] == 1
+    assert gpu["stats"]["lds_state"] == 3      # state and tables in LDS
     assert gpu["stats"]["nstar_max"] >= 3
