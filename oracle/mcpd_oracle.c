@@ -19,7 +19,7 @@
  *   philox4x32_10 ......... rocRAND's own Philox4x32-10 engine (header source)
  *   log-odds terms ......... brute-force posterior ratios (exact enumeration)
  *   score_weights .......... sum to one, uniform floor, max/min ratio = gamma
- *   quantize / site draw ... exact mass identities; chi-square of draws
+ *   quantize / alias ....... exact mass identities of the table; chi-square of draws
  *   cond_p1 (full cond.) ... brute-force pi(x^{i<-1}) / (pi(x^{i<-1}) + pi(x^{i<-0}))
  *   gibbs update + draw .... pi P_w = pi, detailed balance; chi-square vs P_w rows
  *   replication ............ literal H_r sums from the trace; faithfulness;
@@ -132,8 +132,10 @@ typedef struct {
     double a_pos;       /* a_j for y_j = 1 */
     double a_neg;       /* a_j for y_j = 0 */
     double *w;          /* selection weights as given or the score weights */
-    uint32_t *mass;     /* quantized integer masses, sum 2^32 */
-    uint64_t *cum;      /* cum[i] = mass[0] + ... + mass[i] */
+    uint64_t *mass;     /* quantized integer masses, sum 2^32 */
+    int32_t abits;      /* a: the alias table has 2^a columns, 2^a >= n */
+    uint32_t *athr;     /* [2^a] column threshold T_c in [0, 2^(32-a)] */
+    uint32_t *alias;    /* [2^a] column alias A_c */
 } mo_model;
 
 /* a_j = log Pr{y_j|xi=1} - log Pr{y_j|xi=0} (Section "Score-Weighted Update
@@ -226,7 +228,7 @@ static int rem_cmp(const void *a, const void *b)
     return (x->idx < y->idx) ? -1 : (x->idx > y->idx);
 }
 
-int mo_quantize(int32_t n, const double *w, uint32_t *mass)
+int mo_quantize(int32_t n, const double *w, uint64_t *mass)
 {
     if (n <= 0 || n > (1 << 24)) return MO_EINVAL;
     double wsum = 0.0;
@@ -243,8 +245,8 @@ int mo_quantize(int32_t n, const double *w, uint32_t *mass)
         double f = (w[i] / wsum) * S;
         double fl = floor(f);
         uint64_t mi = 1u + (uint64_t)fl;
-        if (mi > 0xFFFFFFFFull) { free(r); return MO_EINVAL; }
-        mass[i] = (uint32_t)mi;
+        if (mi > 4294967296ull) { free(r); return MO_EINVAL; }
+        mass[i] = mi;
         total += mi;
         r[i].rem = f - fl;
         r[i].idx = i;
@@ -254,6 +256,53 @@ int mo_quantize(int32_t n, const double *w, uint32_t *mass)
     qsort(r, (size_t)n, sizeof(rem_t), rem_cmp);
     for (int64_t t = 0; t < D; ++t) mass[r[t].idx] += 1u;
     free(r);
+    return MO_OK;
+}
+
+/* Site sampler (reading; the paper only requires Pr{I_t = i} = w_i with
+ * fixed weights): a Walker alias table (Walker 1977) built by Vose's
+ * procedure (Vose 1991) on the integer masses.  With a = max(1, ceil(log2 n))
+ * there are 2^a columns of capacity K = 2^(32-a); column c < n starts with
+ * mass M_c, columns c >= n with 0.  Columns with mass < K are pushed on the
+ * "small" stack, the others on the "large" stack, in ascending c; then, while
+ * both are non-empty, pop l from small and g from large, set T_l = mass_l,
+ * A_l = g, mass_g -= K - mass_l, and push g back on small (mass_g < K) or
+ * large.  Columns left on either stack get T = K, A = self.  The draw takes
+ * the top a bits of the site word as the column c and the low 32-a bits as r:
+ * I = c if r < T_c, else A_c.  Every step is exact integer arithmetic, so
+ * Pr{I = i} = M_i / 2^32 exactly. */
+static int build_alias(mo_model *M)
+{
+    int32_t a = 1;
+    while (((int64_t)1 << a) < M->n) ++a;
+    const int64_t N = (int64_t)1 << a;
+    const uint64_t K = (uint64_t)1 << (32 - a);
+    uint64_t *mass = (uint64_t *)malloc((size_t)N * sizeof(uint64_t));
+    int64_t *small = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    int64_t *large = (int64_t *)malloc((size_t)N * sizeof(int64_t));
+    M->athr = (uint32_t *)malloc((size_t)N * sizeof(uint32_t));
+    M->alias = (uint32_t *)malloc((size_t)N * sizeof(uint32_t));
+    if (!mass || !small || !large || !M->athr || !M->alias) {
+        free(mass); free(small); free(large);
+        return MO_ENOMEM;
+    }
+    int64_t ns = 0, nl = 0;
+    for (int64_t c = 0; c < N; ++c) {
+        mass[c] = c < M->n ? M->mass[c] : 0u;
+        if (mass[c] < K) small[ns++] = c; else large[nl++] = c;
+    }
+    while (ns > 0 && nl > 0) {
+        const int64_t l = small[--ns];
+        const int64_t g = large[--nl];
+        M->athr[l] = (uint32_t)mass[l];
+        M->alias[l] = (uint32_t)g;
+        mass[g] -= K - mass[l];
+        if (mass[g] < K) small[ns++] = g; else large[nl++] = g;
+    }
+    while (nl > 0) { const int64_t g = large[--nl]; M->athr[g] = (uint32_t)K; M->alias[g] = (uint32_t)g; }
+    while (ns > 0) { const int64_t l = small[--ns]; M->athr[l] = (uint32_t)K; M->alias[l] = (uint32_t)l; }
+    M->abits = a;
+    free(mass); free(small); free(large);
     return MO_OK;
 }
 
@@ -269,10 +318,9 @@ mo_model *mo_model_create(int32_t n, int32_t m, const int32_t *row_ptr, const in
     M->pool_idx = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
     M->y = (uint8_t *)malloc((size_t)m);
     M->w = (double *)malloc((size_t)n * sizeof(double));
-    M->mass = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
-    M->cum = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    M->mass = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
     double *s = (double *)malloc((size_t)n * sizeof(double));
-    if (!M->row_ptr || !M->pool_idx || !M->y || !M->w || !M->mass || !M->cum || !s) goto fail;
+    if (!M->row_ptr || !M->pool_idx || !M->y || !M->w || !M->mass || !s) goto fail;
     memcpy(M->row_ptr, row_ptr, (size_t)(n + 1) * sizeof(int32_t));
     if (nnz) memcpy(M->pool_idx, pool_idx, (size_t)nnz * sizeof(int32_t));
     memcpy(M->y, y, (size_t)m);
@@ -285,13 +333,13 @@ mo_model *mo_model_create(int32_t n, int32_t m, const int32_t *row_ptr, const in
         goto fail;
     }
     if (mo_quantize(n, M->w, M->mass)) goto fail;
-    uint64_t c = 0;
-    for (int32_t i = 0; i < n; ++i) { c += M->mass[i]; M->cum[i] = c; }
+    if (build_alias(M)) goto fail;
     free(s);
     return M;
 fail:
     free(s);
-    free(M->row_ptr); free(M->pool_idx); free(M->y); free(M->w); free(M->mass); free(M->cum);
+    free(M->row_ptr); free(M->pool_idx); free(M->y); free(M->w); free(M->mass);
+    free(M->athr); free(M->alias);
     free(M);
     return NULL;
 }
@@ -299,25 +347,32 @@ fail:
 void mo_model_free(mo_model *M)
 {
     if (!M) return;
-    free(M->row_ptr); free(M->pool_idx); free(M->y); free(M->w); free(M->mass); free(M->cum);
+    free(M->row_ptr); free(M->pool_idx); free(M->y); free(M->w); free(M->mass);
+    free(M->athr); free(M->alias);
     free(M);
 }
 
-void mo_model_masses(const mo_model *M, uint32_t *mass)
+void mo_model_masses(const mo_model *M, uint64_t *mass)
 {
-    memcpy(mass, M->mass, (size_t)M->n * sizeof(uint32_t));
+    memcpy(mass, M->mass, (size_t)M->n * sizeof(uint64_t));
 }
 
-/* Site draw: I = the smallest i with cum[i] > site_word (inverse of the
- * integer CDF; Pr{I = i} = M_i / 2^32). */
+/* Site draw from the alias table (see build_alias). */
 static int32_t site_of(const mo_model *M, uint32_t s)
 {
-    int32_t lo = 0, hi = M->n - 1;
-    while (lo < hi) {
-        int32_t mid = lo + (hi - lo) / 2;
-        if (M->cum[mid] > (uint64_t)s) hi = mid; else lo = mid + 1;
-    }
-    return lo;
+    const int32_t a = M->abits;
+    const uint32_t c = s >> (32 - a);
+    const uint32_t r = s & (uint32_t)((((uint64_t)1) << (32 - a)) - 1u);
+    return (int32_t)(r < M->athr[c] ? c : M->alias[c]);
+}
+
+/* The alias table (tests): 2^a thresholds and aliases; returns a. */
+int32_t mo_model_alias(const mo_model *M, uint32_t *thr, uint32_t *alias)
+{
+    const int64_t N = (int64_t)1 << M->abits;
+    if (thr) memcpy(thr, M->athr, (size_t)N * sizeof(uint32_t));
+    if (alias) memcpy(alias, M->alias, (size_t)N * sizeof(uint32_t));
+    return M->abits;
 }
 
 int32_t mo_site(const mo_model *M, uint32_t site_word) { return site_of(M, site_word); }

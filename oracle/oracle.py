@@ -66,6 +66,8 @@ def lib():
                                           C.c_double, C.c_double, vp]
             L.mo_model_free.argtypes = [vp]
             L.mo_model_masses.argtypes = [vp, vp]
+            L.mo_model_alias.restype = C.c_int32
+            L.mo_model_alias.argtypes = [vp, vp, vp]
             L.mo_site.restype = C.c_int32
             L.mo_site.argtypes = [vp, C.c_uint32]
             L.mo_conditional.restype = C.c_double
@@ -124,7 +126,7 @@ def score_weights(inst):
 
 def quantize(w):
     w = np.ascontiguousarray(w, np.float64)
-    mass = np.zeros(len(w), np.uint32)
+    mass = np.zeros(len(w), np.uint64)
     rc = lib().mo_quantize(len(w), _ptr(w), _ptr(mass))
     if rc:
         raise ValueError(f"mo_quantize failed ({rc})")
@@ -152,9 +154,16 @@ class Model:
             self.h = None
 
     def masses(self):
-        out = np.zeros(self.n, np.uint32)
+        out = np.zeros(self.n, np.uint64)
         lib().mo_model_masses(self.h, _ptr(out))
         return out
+
+    def alias_table(self):
+        a = lib().mo_model_alias(self.h, None, None)
+        thr = np.zeros(1 << a, np.uint32)
+        alias = np.zeros(1 << a, np.uint32)
+        lib().mo_model_alias(self.h, _ptr(thr), _ptr(alias))
+        return a, thr, alias
 
     def site(self, word):
         return lib().mo_site(self.h, word)

@@ -16,6 +16,7 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: longer CPU test")
 
 
-def pytest_runtest_logstart(nodeid, location):
-    # name the case before it runs, so a run that dies mid-test still says which
-    print(f"\n[start] {nodeid}", flush=True)
+def pytest_runtest_setup(item):
+    # name a GPU case before it runs, so a run that dies mid-test still says which
+    if item.get_closest_marker("gpu") is not None:
+        print(f"\n[start] {item.nodeid}", flush=True)

@@ -235,20 +235,45 @@ def test_scores_reduce_to_naive_ranking():
             assert abs(s[i] - d * math.log(R)) < 1e-12 * max(1, abs(s[i]))
 
 
-def test_quantized_masses_and_site_inverse_cdf():
-    inst, _ = I.paper_shaped()
-    _, w = O.score_weights(inst)
-    M = O.Model(inst)
+@pytest.mark.parametrize("which", ["paper", "tiny", "skewed", "one"])
+def test_quantized_masses_and_alias_table_exact(which):
+    if which == "paper":
+        inst, _ = I.paper_shaped()
+        M = O.Model(inst)
+        _, w = O.score_weights(inst)
+    elif which == "tiny":
+        inst, _ = I.tiny_plain()
+        M = O.Model(inst)
+        _, w = O.score_weights(inst)
+    elif which == "skewed":
+        inst = I.make_instance("sk", 300, 40, 3, 3, 0.1, 0.1, prior=0.01, seed=1)
+        w = np.geomspace(1e-6, 1.0, inst.n)
+        M = O.Model(inst, weights=w)
+        w = w / w.sum()
+    else:
+        inst = I.identity_instance(1, 0.1, 0.1, 0.3)
+        M = O.Model(inst)
+        w = np.ones(1)
     mass = M.masses().astype(np.int64)
     n = inst.n
     assert mass.sum() == 1 << 32 and mass.min() >= 1
     assert np.all(np.abs(mass - w * 2.0 ** 32) <= 2 + n * w)
-    cum = np.cumsum(mass)
-    lo = np.concatenate([[0], cum[:-1]])
-    # Every site word in [lo_i, cum_i) maps to clone i, so Pr{I=i} = M_i/2^32.
-    for i in list(range(0, n, 7)) + [n - 1]:
-        assert M.site(int(lo[i])) == i
-        assert M.site(int(cum[i] - 1)) == i
+    # Alias table: 2^a >= n columns of capacity K = 2^(32-a).  A site word s
+    # picks column c = s >> (32-a) and keeps c when s mod K < T_c, else A_c,
+    # so clone i receives sum_c [c = i] T_c + [A_c = i] (K - T_c) site words.
+    a, T, A = M.alias_table()
+    N, K = 1 << a, 1 << (32 - a)
+    assert N >= n and (a == 1 or N // 2 < n)
+    assert np.all(T <= K)
+    got = np.zeros(N, np.int64)
+    np.add.at(got, np.arange(N), T.astype(np.int64))
+    np.add.at(got, A.astype(np.int64), K - T.astype(np.int64))
+    assert np.array_equal(got[:n], mass)
+    assert np.all(got[n:] == 0) and np.all(A < n)
+    rng = np.random.default_rng(5)
+    for s_ in rng.integers(0, 1 << 32, size=200):
+        c, r = int(s_) >> (32 - a), int(s_) & (K - 1)
+        assert M.site(int(s_)) == (c if r < T[c] else int(A[c]))
     # user weights with a tiny entry still get a positive mass
     w2 = np.ones(50); w2[3] = 1e-30
     m2 = O.quantize(w2)
