@@ -5,7 +5,8 @@ workload: 1298 clones, 97 pools, degree 5, 3 positives, fp 0.05, fn 0.10,
 q = 3/1298, budget 2^28 progress units over 65536 slots (B = 4096), window
 k = 131, l = 1298 (one sweep), score weights.  The instance tables are
 resident in device memory before the timed region; every step runs the
-sampler kernel, the integer bucket reduction and the final FP64 division.
+sampler kernel, the integer bucket reduction and the final FP64 division,
+with a new seed per step.
 
 Prints one JSON line.  Only one GPU is used; --gpus N > 1 exits.
 """
@@ -21,28 +22,44 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic cost per progress unit ("Roofline"):
-#   VALU issue slots of the minimal per-draw work at degree d,
-#   LDS bytes of the per-pair state touched at degree d.
-PHILOX_SLOTS_PER_DRAW = 50          # half a Philox4x32-10 block: 10 x (2 quarter-rate mad_u64 + 2 xor3) / 2
+# MI355X unit counts and clock: 256 CUs x 4 SIMDs x 16 lanes, 2.4 GHz.
+CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
+# Peak 32-bit VALU issue: one lane-op per lane per clock (no packed ops).
+ALU_PEAK_OPS = CUS * SIMDS * LANES * CLOCK              # 3.93e13 lane-ops/s
 
 
-def valu_slots_per_draw(d: float) -> float:
-    # site draw 3 + state bit read 3 + per pool 9 + threshold/decision 5 + loop 3
-    return PHILOX_SLOTS_PER_DRAW + 3 + 3 + 9 * d + 5 + 3
+def alg_ops_per_update(d: float) -> float:
+    """Algorithmic 32-bit lane-op slots of one coupled update (after meeting,
+    which is where the chains spend almost all draws): half a Philox4x32-10
+    block (10 rounds x (2 quarter-rate 32x32->64 products = 8 slots + 2
+    three-input xors)) = 50, the alias site draw (shift, mask, compare,
+    select) = 4, the free test and pattern step of each of the d pools = 4d,
+    the threshold index and 53-bit comparison = 4."""
+    return 50.0 + 4.0 + 4.0 * d + 4.0
 
 
-def lds_bytes_per_draw(d: float) -> float:
-    # one dword of state bits + one count dword per pool of the drawn clone
-    return 4.0 * (1 + d)
+def lds_bytes_per_update(d: float) -> float:
+    """Algorithmic LDS bytes of one update: the alias word (4), the clone row
+    (8), one bit word (4) and d count words (4d) of the pair, one threshold (8)."""
+    return 4.0 + 8.0 + 4.0 + 4.0 * d + 8.0
 
 
-MI355X = dict(cus=256, clock_hz=2.4e9, simd_per_cu=4, lanes_per_simd_clk=16, hbm_Bps=8.0e12)
-
-
-def alu_peak_slots_per_s():
-    c = MI355X
-    return c["cus"] * c["simd_per_cu"] * c["lanes_per_simd_clk"] * c["clock_hz"]
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 summary, or None when
+    the sampler source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sampler_knill1298x97_hbm.md")
+    src = os.path.join(ROOT, "paper_2608_30239_amd", "csrc", "mcpd_sampler.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and
+                  line.split(": ", 1)[0] in ("kernel_sha256", "traffic_bytes_per_launch"))
+    if fields.get("kernel_sha256") != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(inst, rp, threads: int, slots: int):
@@ -54,8 +71,20 @@ def cpu_baseline(inst, rp, threads: int, slots: int):
     dt = time.perf_counter() - t0
     units = r["stats"]["retained_units"] + r["stats"]["discarded_units"]
     return dict(value=units / dt, unit="coupled Gibbs updates/s", cores=threads, kind="oracle",
-                sample=f"{slots} of {rp.slots} slots of the same workload (B={B}), "
-                       f"{units} progress units in {dt:.2f} s")
+                sample=f"{slots} of the {rp.slots} slots of the same workload (B={B}); "
+                       f"{units} coupled updates in {dt:.2f} s")
+
+
+def copy_calibration(mib: int, reps: int):
+    """A plain device copy of known size, for scaling FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "reps": reps}), flush=True)
 
 
 def main():
@@ -65,10 +94,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slots", type=int, default=16384)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib, max(1, args.steps))
+        return
 
     from paper_2608_30239_amd import instances as I
     from paper_2608_30239_amd import native as N
@@ -76,8 +110,8 @@ def main():
     inst, rp = I.paper_shaped()
     d_mean = float(inst.degrees().mean())
     dec = N.Decoder(inst)
-    for _ in range(args.warmup):
-        dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed)
+    for i in range(args.warmup):
+        dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + 1000 + i)
     units = 0
     kernel_ms = []
     t0 = time.perf_counter()
@@ -91,12 +125,19 @@ def main():
     value = units / dt
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     units_per_launch = units / args.steps
-    slots_alg = valu_slots_per_draw(d_mean) * units_per_launch
-    achieved = slots_alg / avg_kernel_s
-    peak = alu_peak_slots_per_s()
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "Tslot/s",
-                "frac": achieved / peak, "traffic": None,
-                "lds_achieved_TBps": lds_bytes_per_draw(d_mean) * units_per_launch / avg_kernel_s / 1e12}
+    achieved_ops = alg_ops_per_update(d_mean) * units_per_launch / avg_kernel_s
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved_ops / 1e12,
+        "peak": ALU_PEAK_OPS / 1e12,
+        "unit": "Tops/s",
+        "frac": achieved_ops / ALU_PEAK_OPS,
+        "traffic": measured_traffic(),
+        "kernel": "mcpd sampler_kernel (state and tables in LDS, 5-entry rows)",
+        "alg_ops_per_update": alg_ops_per_update(d_mean),
+        "lds_bytes_per_update": lds_bytes_per_update(d_mean),
+        "lds_achieved_TBps": lds_bytes_per_update(d_mean) * units_per_launch / avg_kernel_s / 1e12,
+    }
     out = {
         "metric": "coupled Gibbs updates/s",
         "value": value,
@@ -108,11 +149,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int64/u32 (fp64 thresholds)",
+        "dtype": "int64 estimator, u32 state (fp64 thresholds)",
         "data": "synthetic",
-        "config": {"workload": "knill1298x97 paper-shaped: n=1298, m=97, d=5, 3 positives, "
-                               "fp=0.05, fn=0.10, budget 2^28, 65536 slots, k=131, l=1298",
-                   "slots": rp.slots, "budget": rp.budget},
+        "config": {"workload": "knill1298x97 paper-shaped: n=1298, m=97, degree 5, 3 positives, "
+                               "fp=0.05, fn=0.10, q=3/1298, budget 2^28 over 65536 slots, k=131, l=1298",
+                   "slots": rp.slots, "budget": rp.budget, "k": rp.k, "m": rp.m},
         "kernel_ms": avg_kernel_s * 1e3,
         "kernel_updates_per_s": units_per_launch / avg_kernel_s,
         "roofline": roofline,

@@ -59,6 +59,13 @@ typedef struct mcpd_run_opts {
                                (default 32; 1..32; lower values only serve to
                                exercise the low-bit refinement in tests)      */
     uint32_t instance_id;   /* g of the random-number counter (< 2^24), default 0 */
+    uint32_t plan;          /* launch plan (results never depend on it): 0 = auto,
+                               1 = chain state and tables in LDS, 2 = state in
+                               LDS and tables in global memory, 3 = state in
+                               global memory and tables in LDS, 4 = both global;
+                               a plan that does not fit returns MCPD_EINVAL   */
+    uint32_t wg_per_cu;     /* workgroups of 256 lanes per compute unit
+                               (0 = the most that fit, at most 8)              */
     /* Optional host outputs (NULL = not wanted). */
     uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */
     uint64_t *slot_units;   /* [slots] S_p(N*): progress units of the retained  */
@@ -131,8 +138,8 @@ int mcpd_create(int32_t n_clones, int32_t n_pools, const int32_t *row_ptr,
 int mcpd_set_weights(mcpd_instance *inst, const double *w);
 
 /* The weights actually sampled: w_exact [n] host = M_i / 2^32 (may be NULL),
- * mass [n] host = M_i (may be NULL). */
-int mcpd_get_weights(const mcpd_instance *inst, double *w_exact, uint32_t *mass);
+ * mass [n] host = M_i (may be NULL; M_i >= 1, sum 2^32). */
+int mcpd_get_weights(const mcpd_instance *inst, double *w_exact, uint64_t *mass);
 
 /* Run the fixed-budget unbiased estimator (Algorithm 4 over Algorithm 3).
  *   budget   total progress units (one coupled draw = one unit); the per-slot

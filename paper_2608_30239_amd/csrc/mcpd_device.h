@@ -6,19 +6,18 @@
 
 namespace mcpd {
 
-// Clone records: word 0 holds the inclusive upper bound of the clone's site
-// words (M_0 + ... + M_i - 1); the following bytes hold its pools in
-// ascending order, each entry pool | (outcome << top bit), padded with
-// all-ones entries.  A format fixes the entry width and the number of
-// entries the kernel reads (a compile-time loop length).
-enum RecFmt {
-    FMT_U8_4 = 0,   // 8-byte records, 4 one-byte entries (pools < 127)
-    FMT_U8_5 = 1,   // 16-byte records, 5 one-byte entries
-    FMT_U8_8 = 2,   // 16-byte records, 8 one-byte entries
-    FMT_U8_12 = 3,  // 16-byte records, 12 one-byte entries
-    FMT_U16_4 = 4,  // 16-byte records, 4 two-byte entries (pools < 32767)
-    FMT_U16_8 = 5,  // 32-byte records, 8 two-byte entries
-    FMT_U16_12 = 6, // 32-byte records, 12 two-byte entries
+// Clone rows: the pools of one clone in ascending order, each entry
+// pool | (outcome << top bit), padded with all-ones entries.  A format fixes
+// the entry width and the number of entries the kernel reads (a compile-time
+// loop length).
+enum RowFmt {
+    FMT_U8_4 = 0,   // 4-byte rows, 4 one-byte entries (pools < 127)
+    FMT_U8_5 = 1,   // 8-byte rows, 5 one-byte entries
+    FMT_U8_8 = 2,   // 8-byte rows, 8 one-byte entries
+    FMT_U8_12 = 3,  // 16-byte rows, 12 one-byte entries
+    FMT_U16_4 = 4,  // 8-byte rows, 4 two-byte entries (pools < 32767)
+    FMT_U16_8 = 5,  // 16-byte rows, 8 two-byte entries
+    FMT_U16_12 = 6, // 32-byte rows, 12 two-byte entries
     FMT_COUNT = 7
 };
 
@@ -28,20 +27,25 @@ __host__ __device__ constexpr int fmt_entries(int f)
          : f == FMT_U16_4 ? 4 : f == FMT_U16_8 ? 8 : 12;
 }
 __host__ __device__ constexpr bool fmt_wide(int f) { return f >= FMT_U16_4; }
-__host__ __device__ constexpr int fmt_rec_bytes(int f)
+__host__ __device__ constexpr int fmt_row_bytes(int f)
 {
-    return f == FMT_U8_4 ? 8 : (f == FMT_U16_8 || f == FMT_U16_12) ? 32 : 16;
+    return f == FMT_U8_4 ? 4 : (f == FMT_U8_5 || f == FMT_U8_8 || f == FMT_U16_4) ? 8
+         : (f == FMT_U8_12 || f == FMT_U16_8) ? 16 : 32;
 }
 
 // Per-instance read-only tables in device memory.
 struct DevTables {
-    const uint32_t *guide;  // [1 << gbits]: smallest i with cum_hi(i) >= b << gshift
-    const uint32_t *recs;   // [n * rec_bytes / 4] clone records
+    // Alias table of the site draw: 2^abits columns of capacity
+    // K = 2^(32 - abits); word c = T_c | A_c << (32 - abits), where column c
+    // keeps clone c when the coin (low 32 - abits bits of the site word) is
+    // below T_c and otherwise gives clone A_c.  A column that always keeps
+    // its clone is stored as T_c = 0, A_c = c.
+    const uint32_t *alias;
+    const uint32_t *rows;   // [n * row_bytes / 4] clone rows
     const uint64_t *thr;    // [2^(dmax+1) - 1]: floor(p * 2^53) per ordered free-pool outcome pattern
     int32_t n, m, dmax, fmt;
-    uint32_t gshift;        // 32 - gbits
-    uint32_t gbits;
-    uint32_t rec_bytes;
+    uint32_t abits;
+    uint32_t row_bytes;
     uint32_t thr_len;
 };
 
@@ -60,7 +64,7 @@ struct RunArgs {
     uint32_t hist_bins, hist_width;
     uint32_t words_bits, words_cnt; // per-lane state words (bit pairs, count pairs)
     uint32_t list_cap;  // touched-list capacity per lane
-    uint32_t tab_off_thr, tab_off_guide, tab_off_recs, tab_bytes; // LDS table layout (bytes)
+    uint32_t tab_off_thr, tab_off_alias, tab_off_rows, tab_bytes; // LDS table layout (bytes)
     uint32_t nbuckets;  // rows of S1/S2
     // per-lane storage (lanes_total = gridDim.x * blockDim.x)
     int64_t *acc;       // [lanes_total * n] spilled numerators (kept zero between slots)

@@ -5,8 +5,8 @@
 // score weights "only once, before the chain starts", Section
 // "Score-Weighted Update Gibbs Sampler"):
 //   * score weights w (or caller weights) -> integer masses M_i, sum 2^32
-//   * inclusive cumulative masses and a guide table for the site draw
-//   * clone rows: pool index | outcome << 15, padded to a power of two
+//   * the alias table of the site draw
+//   * clone rows: pool index | outcome << top bit, ascending
 //   * the decision thresholds floor(p * 2^53) for every ordered pattern of
 //     free-pool outcomes (at most 2^(dmax+1) - 1 values of the FP64 log-odds)
 #include <hip/hip_runtime.h>
@@ -22,18 +22,17 @@
 #include "mcpd_device.h"
 
 struct mcpd_instance {
-    int32_t n = 0, m = 0, dmax = 0, fmt = 0, gbits = 1;
-    uint32_t rec_bytes = 16, thr_len = 1;
-    std::vector<uint8_t> rows;   // row bytes of each record (record minus its first word)
+    int32_t n = 0, m = 0, dmax = 0, fmt = 0, abits = 1;
+    uint32_t row_bytes = 8, thr_len = 1;
     double fp = 0, fn = 0, q = 0;
     std::vector<int32_t> row_ptr, pool_idx;
     std::vector<uint8_t> y;
-    std::vector<uint32_t> mass;
+    std::vector<uint64_t> mass;
     hipStream_t stream = nullptr;
     int device = 0;
     int cus = 0;
     // device tables
-    uint32_t *d_guide = nullptr, *d_recs = nullptr;
+    uint32_t *d_alias = nullptr, *d_rows = nullptr;
     uint64_t *d_thr = nullptr;
     // workspace reused across runs
     int64_t *d_acc = nullptr;
@@ -79,10 +78,10 @@ constexpr uint32_t LIST_CAP = 64;
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// LDS bytes of the table copy: thresholds, guide, clone records.
-size_t table_bytes(size_t thr_len, int gbits, size_t n, size_t rec_bytes)
+// LDS bytes of the table copy: thresholds, alias table, clone rows.
+size_t table_bytes(size_t thr_len, int abits, size_t n, size_t row_bytes)
 {
-    return align16(align16(align16(thr_len * 8) + ((size_t)4 << gbits)) + n * rec_bytes);
+    return align16(align16(align16(thr_len * 8) + ((size_t)4 << abits)) + n * row_bytes);
 }
 constexpr size_t LDS_BYTES = 160 * 1024;
 
@@ -149,7 +148,7 @@ void score_weights(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *
 
 // Integer masses M_i >= 1 with sum 2^32: 1 + floor(v_i (2^32 - n)), the
 // leftover units to the largest remainders (ties to the lower index).
-int quantize(int32_t n, const double *w, std::vector<uint32_t> &mass)
+int quantize(int32_t n, const double *w, std::vector<uint64_t> &mass)
 {
     double wsum = 0.0;
     for (int32_t i = 0; i < n; ++i) {
@@ -165,8 +164,8 @@ int quantize(int32_t n, const double *w, std::vector<uint32_t> &mass)
         const double f = (w[i] / wsum) * S;
         const double fl = std::floor(f);
         const uint64_t mi = 1u + (uint64_t)fl;
-        if (mi > 0xFFFFFFFFull) return fail(MCPD_EINVAL, "weight quantization overflow");
-        mass[i] = (uint32_t)mi;
+        if (mi > 4294967296ull) return fail(MCPD_EINVAL, "weight quantization overflow");
+        mass[i] = mi;
         total += mi;
         rem[i] = {f - fl, i};
     }
@@ -188,33 +187,47 @@ int upload(T **dptr, const std::vector<T> &h, hipStream_t s)
     return MCPD_OK;
 }
 
-// Site-draw tables from the masses: clone records {inclusive cumulative
-// mass, pools} and the guide table.
+// Alias table of the site draw from the integer masses (Walker's method,
+// built by Vose's procedure): 2^a >= n columns of capacity K = 2^(32-a);
+// columns under capacity go on the "small" stack and the others on the
+// "large" stack in ascending order; pairs are popped from the tops, the
+// small column keeps its mass as threshold and the large one as alias, and
+// the large one returns to whichever stack its remaining mass belongs.
+// Integer arithmetic keeps Pr{I = i} = M_i / 2^32 exact.  Packed words:
+// T_c | A_c << (32 - a), a column that always keeps its clone as 0 | c << (32 - a).
 int upload_site_tables(mcpd_instance *I)
 {
-    const int32_t n = I->n;
-    const size_t rw = I->rec_bytes / 4;
-    std::vector<uint32_t> recs((size_t)n * rw);
-    std::vector<uint32_t> cum(n);
-    uint64_t c = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        c += I->mass[i];
-        cum[i] = (uint32_t)(c - 1);
-        recs[(size_t)i * rw] = cum[i];
-        std::memcpy(&recs[(size_t)i * rw + 1], &I->rows[(size_t)i * (I->rec_bytes - 4)], I->rec_bytes - 4);
+    const int a = I->abits;
+    const size_t N = (size_t)1 << a;
+    const uint64_t K = (uint64_t)1 << (32 - a);
+    std::vector<uint64_t> mass(N, 0);
+    for (int32_t i = 0; i < I->n; ++i) mass[i] = I->mass[i];
+    std::vector<size_t> small, large;
+    small.reserve(N);
+    large.reserve(N);
+    for (size_t c = 0; c < N; ++c) (mass[c] < K ? small : large).push_back(c);
+    std::vector<uint32_t> words(N);
+    const uint32_t sh = 32u - (uint32_t)a;
+    while (!small.empty() && !large.empty()) {
+        const size_t l = small.back();
+        small.pop_back();
+        const size_t g = large.back();
+        large.pop_back();
+        words[l] = (uint32_t)mass[l] | ((uint32_t)g << sh);
+        mass[g] -= K - mass[l];
+        (mass[g] < K ? small : large).push_back(g);
     }
-    const uint32_t G = 1u << I->gbits;
-    const uint32_t shift = 32u - (uint32_t)I->gbits;
-    std::vector<uint32_t> guide(G);
-    int32_t i = 0;
-    for (uint32_t b = 0; b < G; ++b) {
-        const uint64_t lo = (uint64_t)b << shift;
-        while ((uint64_t)cum[i] < lo) ++i;
-        guide[b] = (uint32_t)i;
+    for (size_t c : large) words[c] = (uint32_t)c << sh;
+    for (size_t c : small) words[c] = (uint32_t)c << sh;
+    // Every draw must land on a real clone: aliases below n, and columns
+    // past n (mass 0) never keep themselves.
+    const uint32_t tmask = (uint32_t)(K - 1);
+    for (size_t c = 0; c < N; ++c) {
+        const uint32_t A = words[c] >> sh, T = words[c] & tmask;
+        if (A >= (uint32_t)I->n || (c >= (size_t)I->n && T != 0))
+            return fail(MCPD_EINVAL, "internal: alias table maps outside the clones");
     }
-    int rc = upload(&I->d_recs, recs, I->stream);
-    if (rc) return rc;
-    return upload(&I->d_guide, guide, I->stream);
+    return upload(&I->d_alias, words, I->stream);
 }
 
 void free_ptr(void *p)
@@ -224,7 +237,7 @@ void free_ptr(void *p)
 
 void release(mcpd_instance *I)
 {
-    free_ptr(I->d_guide); free_ptr(I->d_recs); free_ptr(I->d_thr); free_ptr(I->d_lane_stats);
+    free_ptr(I->d_alias); free_ptr(I->d_rows); free_ptr(I->d_thr); free_ptr(I->d_lane_stats);
     free_ptr(I->d_acc); free_ptr(I->d_lists); free_ptr(I->d_gstate);
     free_ptr(I->d_S1); free_ptr(I->d_S2); free_ptr(I->d_small);
     free_ptr(I->d_slot_nstar); free_ptr(I->d_slot_units);
@@ -303,26 +316,10 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     } else {
         I->fmt = dmax <= 4 ? mcpd::FMT_U16_4 : dmax <= 8 ? mcpd::FMT_U16_8 : mcpd::FMT_U16_12;
     }
-    I->rec_bytes = (uint32_t)mcpd::fmt_rec_bytes(I->fmt);
-    int gb = 1;
-    while ((1 << gb) < n) ++gb;
-    gb = std::min(gb, 24);
-    {
-        // Halve the guide (at most twice) when that lets the chain state of
-        // 256 lanes and all tables share the LDS.
-        const size_t state = ((size_t)(n + 15) / 16 + (size_t)(m + 1) / 2) * 256 * 4 + 64 * 4;
-        const size_t thr_len = ((size_t)2 << dmax) - 1;
-        const int full = gb;
-        if (state + table_bytes(thr_len, full, n, I->rec_bytes) > LDS_BYTES) {
-            for (int cut = 1; cut <= 2 && full - cut >= 1; ++cut) {
-                if (state + table_bytes(thr_len, full - cut, n, I->rec_bytes) <= LDS_BYTES) {
-                    gb = full - cut;
-                    break;
-                }
-            }
-        }
-    }
-    I->gbits = gb;
+    I->row_bytes = (uint32_t)mcpd::fmt_row_bytes(I->fmt);
+    int ab = 1;
+    while ((1 << ab) < n) ++ab;
+    I->abits = ab;
     I->row_ptr.assign(row_ptr, row_ptr + n + 1);
     I->pool_idx.assign(pool_idx, pool_idx + row_ptr[n]);
     I->y.assign(y, y + m);
@@ -334,22 +331,23 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     rc = quantize(n, w.data(), I->mass);
     if (rc) { delete I; return rc; }
 
-    // record payload: entry = pool | outcome << (top bit), ascending, padded with all-ones
-    const size_t pay = I->rec_bytes - 4;
-    I->rows.assign((size_t)n * pay, 0xFFu);
+    // rows: entry = pool | outcome << (top bit), ascending, padded with all-ones
+    std::vector<uint8_t> rowb((size_t)n * I->row_bytes, 0xFFu);
     for (int32_t i = 0; i < n; ++i) {
         for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
             const uint32_t j = (uint32_t)pool_idx[e], yj = y[pool_idx[e]];
-            const size_t at = (size_t)i * pay;
+            const size_t at = (size_t)i * I->row_bytes;
             const int32_t pos = e - row_ptr[i];
             if (!mcpd::fmt_wide(I->fmt)) {
-                I->rows[at + pos] = (uint8_t)(j | (yj << 7));
+                rowb[at + pos] = (uint8_t)(j | (yj << 7));
             } else {
                 const uint16_t v = (uint16_t)(j | (yj << 15));
-                std::memcpy(&I->rows[at + 2 * pos], &v, 2);
+                std::memcpy(&rowb[at + 2 * pos], &v, 2);
             }
         }
     }
+    std::vector<uint32_t> rows(rowb.size() / 4);
+    std::memcpy(rows.data(), rowb.data(), rowb.size());
 
     // thresholds for every ordered pattern of free-pool outcomes: the FP64
     // sum lq + a_{1st} + a_{2nd} + ... in ascending pool order
@@ -373,7 +371,8 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     if (e != hipSuccess) { delete I; return hip_fail(e, "hipGetDevice"); }
     e = hipDeviceGetAttribute(&I->cus, hipDeviceAttributeMultiprocessorCount, I->device);
     if (e != hipSuccess) { delete I; return hip_fail(e, "hipDeviceGetAttribute"); }
-    if ((rc = upload(&I->d_thr, thr, I->stream)) || (rc = upload_site_tables(I))) {
+    if ((rc = upload(&I->d_thr, thr, I->stream)) || (rc = upload(&I->d_rows, rows, I->stream)) ||
+        (rc = upload_site_tables(I))) {
         release(I);
         delete I;
         return rc;
@@ -392,7 +391,7 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
 int mcpd_set_weights(mcpd_instance *I, const double *w)
 {
     if (!I) return fail(MCPD_EINVAL, "null instance");
-    std::vector<uint32_t> mass;
+    std::vector<uint64_t> mass;
     int rc;
     if (w) {
         rc = quantize(I->n, w, mass);
@@ -410,7 +409,7 @@ int mcpd_set_weights(mcpd_instance *I, const double *w)
     return MCPD_OK;
 }
 
-int mcpd_get_weights(const mcpd_instance *I, double *w_exact, uint32_t *mass)
+int mcpd_get_weights(const mcpd_instance *I, double *w_exact, uint64_t *mass)
 {
     if (!I) return fail(MCPD_EINVAL, "null instance");
     for (int32_t i = 0; i < I->n; ++i) {
@@ -444,11 +443,10 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
 
     mcpd::RunArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.T.guide = I->d_guide; a.T.recs = I->d_recs; a.T.thr = I->d_thr;
+    a.T.alias = I->d_alias; a.T.rows = I->d_rows; a.T.thr = I->d_thr;
     a.T.n = n; a.T.m = I->m; a.T.dmax = I->dmax; a.T.fmt = I->fmt;
-    a.T.gshift = 32u - (uint32_t)I->gbits;
-    a.T.gbits = (uint32_t)I->gbits;
-    a.T.rec_bytes = I->rec_bytes;
+    a.T.abits = (uint32_t)I->abits;
+    a.T.row_bytes = I->row_bytes;
     a.T.thr_len = I->thr_len;
     a.B = B;
     a.capmax = opts.max_steps ? (uint32_t)std::max<uint64_t>(opts.max_steps, m) : 0xFFFFFFFFu;
@@ -465,11 +463,11 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
     a.list_cap = LIST_CAP;
     a.nbuckets = nbuckets;
 
-    // LDS copy of the read-only tables: thresholds, cumulative masses, guide, rows.
+    // LDS copy of the read-only tables: thresholds, alias table, clone rows.
     a.tab_off_thr = 0;
-    a.tab_off_guide = (uint32_t)align16((size_t)I->thr_len * 8);
-    a.tab_off_recs = (uint32_t)align16(a.tab_off_guide + ((size_t)4 << I->gbits));
-    const size_t tab_bytes = table_bytes(I->thr_len, I->gbits, n, I->rec_bytes);
+    a.tab_off_alias = (uint32_t)align16((size_t)I->thr_len * 8);
+    a.tab_off_rows = (uint32_t)align16(a.tab_off_alias + ((size_t)4 << I->abits));
+    const size_t tab_bytes = table_bytes(I->thr_len, I->abits, n, I->row_bytes);
     a.tab_bytes = tab_bytes > LDS_BYTES ? 0u : (uint32_t)tab_bytes;
 
     // Launch plan.  Chain state in LDS needs at least one full wave per SIMD
@@ -483,14 +481,26 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
         if (tl && !a.tab_bytes) return false;
         return mcpd::sampler_lds_bytes(a, L, sl, tl) <= LDS_BYTES;
     };
-    if (fits(256, true, true)) { lds_state = lds_tables = true; }
-    else if (fits(256, true, false)) { lds_state = true; }
-    else { lds_tables = fits(256, false, true); }
+    if (opts.plan > 4) return fail(MCPD_EINVAL, "plan must be 0..4");
+    if (opts.plan == 0) {
+        if (fits(256, true, true)) { lds_state = lds_tables = true; }
+        else if (fits(256, true, false)) { lds_state = true; }
+        else { lds_tables = fits(256, false, true); }
+    } else {
+        lds_state = opts.plan <= 2;
+        lds_tables = opts.plan == 1 || opts.plan == 3;
+        if (!fits(256, lds_state, lds_tables)) return fail(MCPD_EINVAL, "requested plan does not fit in LDS");
+    }
     {
         const size_t per_wg = mcpd::sampler_lds_bytes(a, block, lds_state, lds_tables);
         const size_t by_lds = per_wg ? LDS_BYTES / per_wg : 8;
         const size_t by_waves = lds_state ? 2048 / block : 1024 / block;
         wg_per_cu = std::max<size_t>(1, std::min(by_lds, by_waves));
+        if (opts.wg_per_cu) {
+            if (opts.wg_per_cu > 8 || opts.wg_per_cu > by_lds)
+                return fail(MCPD_EINVAL, "wg_per_cu does not fit");
+            wg_per_cu = opts.wg_per_cu;
+        }
     }
     const size_t max_lanes = (size_t)I->cus * wg_per_cu * (size_t)block;
     const size_t want_lanes = std::min<size_t>(((size_t)slots + block - 1) / block * block, max_lanes);

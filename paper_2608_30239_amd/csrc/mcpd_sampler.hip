@@ -16,12 +16,12 @@
 // laid out structure-of-arrays with the lane index fastest, so that the 64
 // lanes of a wave touching any word index hit 64 distinct banks.  The state
 // lives in LDS when the instance fits, otherwise in global memory with the
-// same layout.  The read-only instance tables (thresholds, guide table and
-// clone records holding the cumulative mass and the pools of each clone) are
-// copied into LDS when they fit, so that a draw touches no global memory.
+// same layout.  The read-only instance tables (thresholds, the alias table
+// of the site draw and the clone rows) are copied into LDS when they fit, so
+// that a draw touches no global memory.
 //
-// A draw is a short chain of LDS round trips: guide -> clone record (site
-// and pools in one read) -> all count words of the clone at once -> the
+// A draw is a short chain of LDS round trips: alias column (site in O(1),
+// no search) -> clone row -> all count words of the clone at once -> the
 // threshold of the free-pool pattern.  Control flow inside a draw is
 // branch-free except for the rare flip, event and bookkeeping paths.
 //
@@ -54,6 +54,7 @@ constexpr uint32_t MODE_RUN = 2;
 constexpr uint32_t MODE_DONE = 3;
 constexpr uint32_t NO_TAG = 0xFFFFFFFFu;
 constexpr int CACHE = 8;
+constexpr uint32_t WG = 256;   // lanes per workgroup (state stride), fixed at launch
 
 // Philox4x32-10 (Salmon et al., SC'11).  The key is wave-uniform, so its
 // schedule stays on the scalar unit.
@@ -96,16 +97,18 @@ struct Lane {
 };
 
 template <int F>
-struct Rec {
+struct Row {
     static constexpr int NE = fmt_entries(F);
     static constexpr bool WIDE = fmt_wide(F);
-    static constexpr int WORDS = fmt_rec_bytes(F) / 4;
+    static constexpr int WORDS = fmt_row_bytes(F) / 4;
     uint32_t w[WORDS];
 
     __device__ __forceinline__ void load(const uint32_t *base, uint32_t I)
     {
         const uint32_t *src = base + (size_t)I * WORDS;
-        if constexpr (WORDS == 2) {
+        if constexpr (WORDS == 1) {
+            w[0] = *src;
+        } else if constexpr (WORDS == 2) {
             const uint2 v = *reinterpret_cast<const uint2 *>(src);
             w[0] = v.x; w[1] = v.y;
         } else if constexpr (WORDS == 4) {
@@ -118,11 +121,10 @@ struct Rec {
             w[4] = u.x; w[5] = u.y; w[6] = u.z; w[7] = u.w;
         }
     }
-    __device__ __forceinline__ uint32_t cum() const { return w[0]; }
     __device__ __forceinline__ uint32_t raw(int e) const
     {
-        if constexpr (WIDE) return (w[1 + (e >> 1)] >> ((e & 1) * 16)) & 0xFFFFu;
-        else return (w[1 + (e >> 2)] >> ((e & 3) * 8)) & 0xFFu;
+        if constexpr (WIDE) return (w[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu;
+        else return (w[e >> 2] >> ((e & 3) * 8)) & 0xFFu;
     }
     __device__ __forceinline__ static bool valid(uint32_t v) { return WIDE ? v != 0xFFFFu : v != 0xFFu; }
     __device__ __forceinline__ static uint32_t pool(uint32_t v) { return WIDE ? (v & 0x7FFFu) : (v & 0x7Fu); }
@@ -134,31 +136,32 @@ struct Sampler {
     const RunArgs &a;
     uint32_t *st;           // this workgroup's state base (LDS or global)
     const uint64_t *thr;    // tables (LDS copies or global)
-    const uint32_t *guide;
-    const uint32_t *recs;
-    uint32_t L;             // lanes per workgroup (state stride)
+    const uint32_t *alias;
+    const uint32_t *rows;
     uint32_t lane;          // lane within the workgroup
     int64_t *acc;           // this lane's spill row
     uint32_t *list;         // this lane's touched list
     uint64_t *ls;           // this lane's statistics
     uint32_t *hist_lds;
 
-    __device__ __forceinline__ uint32_t &bits(uint32_t w) const { return st[w * L + lane]; }
-    __device__ __forceinline__ uint32_t &cnt(uint32_t q) const { return st[(a.words_bits + q) * L + lane]; }
+    __device__ __forceinline__ uint32_t &bits(uint32_t w) const { return st[w * WG + lane]; }
+    __device__ __forceinline__ uint32_t &cnt(uint32_t q) const { return st[(a.words_bits + q) * WG + lane]; }
 
+    // Statistic slots and spill rows belong to one lane: workgroup-scope
+    // atomics keep them in the L2 of the lane's XCD instead of memory.
     __device__ __forceinline__ void stat_add(int i, uint64_t v) const
     {
-        atomicAdd(reinterpret_cast<unsigned long long *>(ls + i), (unsigned long long)v);
+        __hip_atomic_fetch_add(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __device__ __forceinline__ void stat_max(int i, uint64_t v) const
     {
-        atomicMax(reinterpret_cast<unsigned long long *>(ls + i), (unsigned long long)v);
+        __hip_atomic_fetch_max(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
     __device__ void reset_state() const
     {
         const uint32_t nw = a.words_bits + a.words_cnt;
-        for (uint32_t w = 0; w < nw; ++w) st[w * L + lane] = 0u;
+        for (uint32_t w = 0; w < nw; ++w) st[w * WG + lane] = 0u;
     }
 
     // First draw count at which after_step has anything to decide: the end of
@@ -176,7 +179,8 @@ struct Sampler {
 
     __device__ __forceinline__ void spill(Lane &s, uint32_t j, uint64_t v) const
     {
-        atomicAdd(reinterpret_cast<unsigned long long *>(acc + j), (unsigned long long)v);
+        __hip_atomic_fetch_add(reinterpret_cast<uint64_t *>(acc + j), v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
         if (j != s.f0 && j != s.f1) {
             if (s.lc < a.list_cap) list[s.lc] = j;
             s.lc += 1;
@@ -233,56 +237,74 @@ struct Sampler {
         return lo <= (T & ((1ull << (53u - b)) - 1ull)) ? 1u : 0u;
     }
 
-    // One draw t of the current replication with site word sw and U word hw.
-    __device__ __forceinline__ void step(Lane &s, uint32_t sw, uint32_t hw) const
+    // Site of a draw from its site word: alias column from the top bits,
+    // coin from the low bits (one LDS read, no search).
+    __device__ __forceinline__ uint32_t site(uint32_t sw) const
     {
-        using R = Rec<F>;
-        const uint32_t t = s.t;
-        uint32_t I = guide[sw >> a.T.gshift];
-        R rc;
-        rc.load(recs, I);
-        while (rc.cum() < sw) {
-            ++I;
-            rc.load(recs, I);
-        }
-        // all state words of the draw, issued back to back
-        const uint32_t bw_idx = I >> 4;
-        const uint32_t bw = bits(bw_idx);
-        uint32_t cw[R::NE];
+        const uint32_t cb = 32u - a.T.abits;
+        const uint32_t col = sw >> cb;
+        const uint32_t aw = alias[col];
+        const uint32_t kmask = (1u << cb) - 1u;
+        return (sw & kmask) < (aw & kmask) ? col : (aw >> cb);
+    }
+
+    // State words a draw at clone I reads: its bit word and one count word
+    // per pool, issued back to back.
+    struct Loads {
+        uint32_t bw;
+        uint32_t cw[Row<F>::NE];
+    };
+    __device__ __forceinline__ Loads issue(uint32_t I, const Row<F> &rc) const
+    {
+        using R = Row<F>;
+        Loads ld;
+        ld.bw = bits(I >> 4);
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
             const uint32_t v = rc.raw(e);
-            cw[e] = cnt((R::valid(v) ? R::pool(v) : 0u) >> 1);
+            ld.cw[e] = cnt((R::valid(v) ? R::pool(v) : 0u) >> 1);
         }
+        return ld;
+    }
+
+    // The rest of draw t at clone I with U word hw: both chains' free-pool
+    // patterns, thresholds, decisions, state update and estimator events.
+    __device__ __forceinline__ void finish(Lane &s, uint32_t I, const Row<F> &rc, const Loads &ld,
+                                           uint32_t hw) const
+    {
+        using R = Row<F>;
+        const uint32_t t = s.t;
+        const uint32_t bw_idx = I >> 4;
+        const uint32_t bw = ld.bw;
         const uint32_t sh = (I & 15u) << 1;
         const uint32_t xi = (bw >> sh) & 1u;
         const uint32_t yi = (bw >> (sh + 1u)) & 1u;
         const bool updY = (s.tau == 0u) && (t > 0u);
 
-        uint32_t patX = 0, lenX = 0;
+        // free-pool patterns of both chains from the same count words
+        uint32_t patX = 0, lenX = 0, patY = 0, lenY = 0;
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
             const uint32_t v = rc.raw(e);
-            const uint32_t cs = (R::pool(v) & 1u) << 4;
-            const bool f = R::valid(v) && ((cw[e] >> cs) & 0xFFu) == xi;
-            patX = f ? ((patX << 1) | R::outcome(v)) : patX;
-            lenX += f ? 1u : 0u;
+            const bool ok = R::valid(v);
+            const uint32_t o = R::outcome(v);
+            const uint32_t c = ld.cw[e] >> ((R::pool(v) & 1u) << 4);
+            const bool fx = ok && (c & 0xFFu) == xi;
+            const bool fy = ok && ((c >> 8) & 0xFFu) == yi;
+            patX = fx ? ((patX << 1) | o) : patX;
+            lenX += fx ? 1u : 0u;
+            patY = fy ? ((patY << 1) | o) : patY;
+            lenY += fy ? 1u : 0u;
         }
         bool have_lo = false;
         uint64_t lo = 0;
-        const uint32_t xn = decide(s, t, hw, thr[(1u << lenX) - 1u + patX], have_lo, lo);
+        const uint32_t ix = (1u << lenX) - 1u + patX;
+        const uint32_t xn = decide(s, t, hw, thr[ix], have_lo, lo);
         uint32_t yn = yi;
         if (updY) {
-            uint32_t patY = 0, lenY = 0;
-#pragma unroll
-            for (int e = 0; e < R::NE; ++e) {
-                const uint32_t v = rc.raw(e);
-                const uint32_t cs = ((R::pool(v) & 1u) << 4) + 8u;
-                const bool f = R::valid(v) && ((cw[e] >> cs) & 0xFFu) == yi;
-                patY = f ? ((patY << 1) | R::outcome(v)) : patY;
-                lenY += f ? 1u : 0u;
-            }
-            yn = decide(s, t, hw, thr[(1u << lenY) - 1u + patY], have_lo, lo);
+            // the same pattern gives the same threshold, hence the same value
+            const uint32_t iy = (1u << lenY) - 1u + patY;
+            yn = (iy == ix) ? xn : decide(s, t, hw, thr[iy], have_lo, lo);
         }
         const int dx = (int)xn - (int)xi;
         const int dy = (int)yn - (int)yi;
@@ -364,13 +386,15 @@ struct Sampler {
         if (s.lc > 0) {
             if (s.lc <= a.list_cap) {
                 for (uint32_t e = 0; e < s.lc; ++e) {
-                    const uint32_t j = __hip_atomic_load(list + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const int64_t v = (int64_t)atomicExch(reinterpret_cast<unsigned long long *>(acc + j), 0ull);
+                    const uint32_t j = __hip_atomic_load(list + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     if (v != 0) emit(nstar, j, v);
                 }
             } else {
                 for (uint32_t j = 0; j < (uint32_t)a.T.n; ++j) {
-                    const int64_t v = (int64_t)atomicExch(reinterpret_cast<unsigned long long *>(acc + j), 0ull);
+                    const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     if (v != 0) emit(nstar, j, v);
                 }
             }
@@ -447,7 +471,7 @@ template <bool SL, bool TL, int F>
 __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
 {
     extern __shared__ uint32_t smem[];
-    const uint32_t L = blockDim.x;
+    constexpr uint32_t L = WG;
     const uint32_t lane = threadIdx.x;
     const uint32_t words = a.words_bits + a.words_cnt;
     uint32_t *after_state = SL ? smem + (size_t)words * L : smem;
@@ -456,8 +480,8 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
     for (uint32_t b = lane; b < a.hist_bins; b += L) hist_lds[b] = 0u;
     if (TL) {
         copy_to_lds(tab + a.tab_off_thr / 4, a.T.thr, a.T.thr_len * 2u);
-        copy_to_lds(tab + a.tab_off_guide / 4, a.T.guide, 1u << a.T.gbits);
-        copy_to_lds(tab + a.tab_off_recs / 4, a.T.recs, (uint32_t)a.T.n * a.T.rec_bytes / 4u);
+        copy_to_lds(tab + a.tab_off_alias / 4, a.T.alias, 1u << a.T.abits);
+        copy_to_lds(tab + a.tab_off_rows / 4, a.T.rows, (uint32_t)a.T.n * a.T.row_bytes / 4u);
     }
     const size_t gl = (size_t)blockIdx.x * L + lane;
     uint64_t *ls = a.lane_stats + gl * ST_COUNT;
@@ -466,11 +490,10 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
     __syncthreads();
 
     Sampler<SL, TL, F> S{a,
-                         SL ? smem : a.gstate + (size_t)blockIdx.x * words * L,
+                         SL ? smem : a.gstate + (size_t)blockIdx.x * words * WG,
                          TL ? reinterpret_cast<const uint64_t *>(tab + a.tab_off_thr / 4) : a.T.thr,
-                         TL ? tab + a.tab_off_guide / 4 : a.T.guide,
-                         TL ? tab + a.tab_off_recs / 4 : a.T.recs,
-                         L,
+                         TL ? tab + a.tab_off_alias / 4 : a.T.alias,
+                         TL ? tab + a.tab_off_rows / 4 : a.T.rows,
                          lane,
                          a.acc + gl * (size_t)a.T.n,
                          a.lists + gl * (size_t)a.list_cap,
@@ -487,6 +510,14 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
 #pragma unroll
     for (int e = 0; e < CACHE; ++e) { s.ctag[e] = NO_TAG; s.cval[e] = 0; }
     const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+
+    // Pipeline registers: the random block of the current pair of draws
+    // (t, t+1) and the site and row of draw t, fetched one draw ahead.
+    uint32_t w[4] = {0, 0, 0, 0};
+    uint32_t curI = 0;
+    Row<F> cur;
+#pragma unroll
+    for (int i = 0; i < Row<F>::WORDS; ++i) cur.w[i] = 0;
 
     for (;;) {
         if (s.mode != MODE_RUN) {
@@ -515,18 +546,36 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
                 s.tau = 0;
                 s.mu = 0;
                 S.set_limit(s);
+                philox10(0u, s.r, s.p, a.g, k0, k1, w);
+                curI = S.site(w[0]);
+                cur.load(S.rows, curI);
                 s.mode = MODE_RUN;
             }
         }
         if (__all(s.mode == MODE_DONE)) break;
         if (s.mode == MODE_RUN) {
-            uint32_t w[4];
-            philox10(s.t >> 1, s.r, s.p, a.g, k0, k1, w);
-            S.step(s, w[0], w[1]);
+            // draw t (even): its state reads go out first, then the next
+            // random block and draw t+1's site and row while they are in flight
+            const typename Sampler<SL, TL, F>::Loads l0 = S.issue(curI, cur);
+            uint32_t nx[4];
+            philox10((s.t >> 1) + 1u, s.r, s.p, a.g, k0, k1, nx);
+            const uint32_t I1 = S.site(w[2]);
+            Row<F> r1;
+            r1.load(S.rows, I1);
+            S.finish(s, curI, cur, l0, w[1]);
             if (s.t >= s.lim) S.after_step(s);
             if (s.mode == MODE_RUN) {
-                S.step(s, w[2], w[3]);
+                // draw t+1 (odd), with draw t+2's site and row fetched behind it
+                const typename Sampler<SL, TL, F>::Loads l1 = S.issue(I1, r1);
+                const uint32_t I2 = S.site(nx[0]);
+                Row<F> r2;
+                r2.load(S.rows, I2);
+                S.finish(s, I1, r1, l1, w[3]);
                 if (s.t >= s.lim) S.after_step(s);
+                curI = I2;
+                cur = r2;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[i] = nx[i];
             }
         }
     }
@@ -535,7 +584,7 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
     // one atomic per wave.
 #pragma unroll
     for (int i = 0; i < ST_COUNT; ++i) {
-        uint64_t v = __hip_atomic_load(ls + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t v = __hip_atomic_load(ls + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         const bool is_max = (i == ST_TAU_MAX || i == ST_NSTAR_MAX);
         for (int off = 32; off > 0; off >>= 1) {
             const uint64_t o = __shfl_xor(v, off);
@@ -589,6 +638,7 @@ size_t sampler_lds_bytes(const RunArgs &a, int block, bool lds_state, bool lds_t
 
 int launch_sampler(const RunArgs &a, int grid, int block, bool lds_state, bool lds_tables, void *stream)
 {
+    if (block != (int)WG) return (int)hipErrorInvalidValue;   // the state stride is compiled in
     const size_t lds = sampler_lds_bytes(a, block, lds_state, lds_tables);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (lds_state) {

@@ -39,6 +39,8 @@ class RunOpts(C.Structure):
         ("hist_width", C.c_uint32),
         ("u_hi_bits", C.c_uint32),
         ("instance_id", C.c_uint32),
+        ("plan", C.c_uint32),
+        ("wg_per_cu", C.c_uint32),
         ("slot_nstar", C.c_void_p),
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),
@@ -143,7 +145,7 @@ def mcpd_set_weights(h, w=None):
 
 def mcpd_get_weights(h, n):
     w = np.zeros(n)
-    mass = np.zeros(n, np.uint32)
+    mass = np.zeros(n, np.uint64)
     _check(load().mcpd_get_weights(h, _p(w), _p(mass)), "mcpd_get_weights")
     return w, mass
 
