@@ -44,6 +44,7 @@ extern "C" {
 #define MCPD_MAX_CLONES (1 << 24)
 
 typedef struct mcpd_instance mcpd_instance;
+typedef struct mcpd_batch mcpd_batch;
 
 /* Run options.  Initialise with mcpd_run_opts_init() and override fields. */
 typedef struct mcpd_run_opts {
@@ -58,25 +59,36 @@ typedef struct mcpd_run_opts {
     uint32_t u_hi_bits;     /* bits of U taken from the main random block
                                (default 32; 1..32; lower values only serve to
                                exercise the low-bit refinement in tests)      */
-    uint32_t instance_id;   /* g of the random-number counter (< 2^24), default 0 */
-    uint32_t plan;          /* launch plan (results never depend on it): 0 = auto,
-                               1 = chain state and tables in LDS, 2 = state in
-                               LDS and tables in global memory, 3 = state in
-                               global memory and tables in LDS, 4 = both global;
-                               a plan that does not fit returns MCPD_EINVAL   */
-    uint32_t wg_per_cu;     /* workgroups of 256 lanes per compute unit
-                               (0 = the most that fit, at most 8)              */
-    /* Optional host outputs (NULL = not wanted). */
+    uint32_t instance_id;   /* g of the random-number counter (< 2^24), default
+                               0; in a batch, instance i uses instance_id + i */
+    uint32_t plan;          /* placement (results never depend on it): 0 = auto
+                               per instance, 1 = chain state and tables in LDS,
+                               2 = state in LDS and tables in global memory,
+                               3 = state in global memory and tables in LDS,
+                               4 = both global; a plan that does not fit returns
+                               MCPD_EINVAL                                    */
+    uint32_t wg_per_cu;     /* workgroups of 256 lanes per compute unit (0 = auto,
+                               at most 8)                                       */
+    uint32_t ticket_slots;  /* slots per lane that one work ticket stands for
+                               (0 = auto; a ticket sends one workgroup to one
+                               instance)                                      */
+    uint32_t use_graph;     /* batches: 1 = replay a captured HIP graph
+                               (default), 0 = plain stream launches           */
+    uint32_t keep_slot_records; /* batches: keep N*_p and S_p of every slot on
+                               the device for mcpd_batch_slot_records         */
+    uint32_t bucket_rows;   /* rows provided in bucket_sum / bucket_sumsq; must
+                               be >= the largest N*                            */
+    /* Optional host outputs of mcpd_run_unbiased (NULL = not wanted; must be
+       NULL for batches). */
     uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */
     uint64_t *slot_units;   /* [slots] S_p(N*): progress units of the retained  */
     int64_t *bucket_sum;    /* [bucket_rows * n] sum of V_pj over slots with
                                N*_p = row+1 (V = W * slot numerator, exact)     */
     uint64_t *bucket_sumsq; /* [bucket_rows * n * 2] (low, high) words of the
                                128-bit sum of V_pj^2, same grouping            */
-    uint32_t bucket_rows;   /* rows provided; must be >= the largest N*        */
 } mcpd_run_opts;
 
-/* Run statistics (all integers exact). */
+/* Run statistics of one instance (all integers exact). */
 typedef struct mcpd_run_stats {
     uint64_t progress_units;      /* draws executed on the device, including
                                      the replayed draws of rolled-back pairs   */
@@ -92,13 +104,25 @@ typedef struct mcpd_run_stats {
     uint64_t tau_max;
     uint64_t nstar_max;           /* largest N*_p                               */
     uint64_t rollback_units;      /* draws replayed to roll back aborted pairs  */
+    uint64_t list_overflows;      /* slots whose touched-clone list overflowed
+                                     (their numerators were flushed by a scan)  */
     uint64_t lanes;               /* persistent lanes of the launch             */
-    uint32_t lds_state;           /* 1 if chain state was held in LDS           */
-    uint32_t reserved;
-    double kernel_ms;             /* device time of the sampler launch          */
+    uint32_t placement;           /* bit 0: chain state in LDS; bit 1: tables in LDS */
+    uint32_t wg_per_cu;           /* workgroups per CU of the launch            */
+    double kernel_ms;             /* device time: the sampler launch, or for a
+                                     batch replayed as a graph the whole replay
+                                     (key copy, zeroing, sampler, copy back)   */
 } mcpd_run_stats;
 
-/* Defaults: no cap, refill on, 64 bins of n draws, u_hi_bits 32, id 0. */
+/* One measured configuration of mcpd_batch_tune. */
+typedef struct mcpd_tune_entry {
+    uint32_t wg_per_cu;
+    uint32_t ticket_slots;
+    double ms;                    /* sampler time of one full run               */
+} mcpd_tune_entry;
+
+/* Defaults: no cap, refill on, 64 bins of n draws, u_hi_bits 32, id 0,
+ * automatic placement and launch shape, graphs on for batches. */
 void mcpd_run_opts_init(mcpd_run_opts *opts);
 
 /* Score weights of the paper (Section "Score-Weighted Update Gibbs Sampler"):
@@ -157,8 +181,66 @@ int mcpd_run_unbiased(mcpd_instance *inst, uint64_t budget, uint32_t slots, uint
                       uint32_t m, uint64_t seed, const mcpd_run_opts *opts, double *marginals,
                       double *stderr_out, uint64_t *hist, mcpd_run_stats *stats);
 
-/* Release the instance and its device memory (NULL is a no-op). */
+/* Release the instance and its device memory (NULL is a no-op).  Destroy
+ * every batch that holds the instance first. */
 void mcpd_destroy(mcpd_instance *inst);
+
+/* Batches: many instances, each with its own run parameters, in ONE
+ * persistent launch (Algorithm 4 for every instance; slots of different
+ * instances are independent, so they share the device freely).
+ *   insts    host [count] instances (kept by the caller, not copied; they
+ *            must outlive the batch and keep their weights while it runs)
+ *   budget, slots, k, m   host [count] per-instance run parameters, as in
+ *            mcpd_run_unbiased
+ *   opts     shared options (NULL = defaults); instance i draws its random
+ *            numbers with g = opts->instance_id + i, so it gives exactly what
+ *            mcpd_run_unbiased gives with instance_id = opts->instance_id + i
+ *   hip_stream  stream of the batch's device work (NULL = a stream the batch
+ *            creates; graphs cannot be captured on the legacy default stream)
+ * Creation plans the launch: the row format, each instance's placement in
+ * LDS, the work tickets (longest slots first) and the workspace; the first
+ * run captures the device work of a run in a HIP graph (use_graph = 1) that
+ * later runs replay.  Errors: MCPD_EINVAL, MCPD_ENOMEM, MCPD_EDEVICE. */
+int mcpd_batch_create(mcpd_instance *const *insts, int32_t count, const uint64_t *budget,
+                      const uint32_t *slots, const uint32_t *k, const uint32_t *m,
+                      const mcpd_run_opts *opts, void *hip_stream, mcpd_batch **out);
+
+/* Run every instance of the batch with key `seed`.  marginals, stderr_out,
+ * hist: host arrays of count pointers (each as in mcpd_run_unbiased; the
+ * arrays, or any of their entries, may be NULL); stats: host [count] or NULL.
+ * Errors: MCPD_EINVAL, MCPD_EDEVICE, MCPD_ECAP (strict_cap). */
+int mcpd_batch_run(mcpd_batch *batch, uint64_t seed, double *const *marginals,
+                   double *const *stderr_out, uint64_t *const *hist, mcpd_run_stats *stats);
+
+/* Autotuner: run the batch once per candidate launch shape (workgroups per
+ * CU x slots per ticket, within opts' fixed values), time the sampler, keep
+ * the fastest.  The results do not depend on the shape.  entries: host [cap]
+ * or NULL; count receives the number of candidates measured. */
+int mcpd_batch_tune(mcpd_batch *batch, uint64_t seed, mcpd_tune_entry *entries, uint32_t cap,
+                    uint32_t *count);
+
+/* The batch's current launch shape; placement: host [count] or NULL. */
+int mcpd_batch_config(const mcpd_batch *batch, uint32_t *wg_per_cu, uint32_t *ticket_slots,
+                      uint32_t *lanes, uint32_t *placement);
+
+/* Integer bucket sums of instance `index` from the last run, laid out as
+ * opts.bucket_sum / bucket_sumsq of mcpd_run_unbiased (host [rows * n] and
+ * [rows * n * 2]; either may be NULL). */
+int mcpd_batch_buckets(const mcpd_batch *batch, int32_t index, uint32_t rows, int64_t *sum,
+                       uint64_t *sumsq);
+
+/* N*_p and S_p of every slot of instance `index` from the last run (host
+ * [slots]; either may be NULL).  Needs opts.keep_slot_records at creation. */
+int mcpd_batch_slot_records(mcpd_batch *batch, int32_t index, uint32_t *nstar, uint64_t *units);
+
+/* Release a batch (NULL is a no-op); the instances stay. */
+void mcpd_batch_destroy(mcpd_batch *batch);
+
+/* One-shot batch: create, run once, destroy. */
+int mcpd_run_batch(mcpd_instance *const *insts, int32_t count, const uint64_t *budget,
+                   const uint32_t *slots, const uint32_t *k, const uint32_t *m, uint64_t seed,
+                   const mcpd_run_opts *opts, double *const *marginals, double *const *stderr_out,
+                   uint64_t *const *hist, mcpd_run_stats *stats);
 
 /* Static name of an error code. */
 const char *mcpd_strerror(int code);

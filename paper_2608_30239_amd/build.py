@@ -1,4 +1,9 @@
-"""Build the HIP library (libmcpd.so) in-tree for gfx950 with hipcc."""
+"""Build the HIP library (libmcpd.so) in-tree for gfx950 with hipcc.
+
+The sampler is compiled once per clone-row format (each instantiation is a
+large kernel) and once for its dispatcher, in parallel, then linked with the
+host side of the C ABI.
+"""
 
 from __future__ import annotations
 
@@ -6,15 +11,18 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmcpd.so")
-SOURCES = ["mcpd_host.cpp", "mcpd_sampler.hip"]
+N_FORMATS = 7
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+    # only the C ABI is exported
+    "-fvisibility=hidden",
     # no FMA contraction anywhere: the host tables must match the FP64
     # reading bit for bit
     "-ffp-contract=off",
@@ -28,15 +36,35 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
+def jobs():
+    """(source, extra flags, object name) of every compile step."""
+    out = [("mcpd_host.cpp", [], "host.o"), ("mcpd_sampler.hip", [], "sampler.o")]
+    out += [("mcpd_sampler.hip", [f"-DMCPD_FMT={f}"], f"sampler_f{f}.o") for f in range(N_FORMATS)]
+    return out
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source into libmcpd.so (always rebuilds)."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    with tempfile.TemporaryDirectory(prefix="mcpd_build_") as tmpd:
+        procs = []
+        objs = []
+        for src, extra, obj in jobs():
+            o = os.path.join(tmpd, obj)
+            cmd = [hipcc(), *HIPCC_FLAGS, *inc, *extra, "-c", os.path.join(CSRC, src), "-o", o]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((cmd, subprocess.Popen(cmd)))
+            objs.append(o)
+        failed = [cmd for cmd, p in procs if p.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, failed[0])
+        tmp = LIB + f".tmp{os.getpid()}"
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
     return LIB
 
 

@@ -2,6 +2,7 @@
 // Not part of the public ABI (include/mcpd.h).
 #pragma once
 
+#include <stddef.h>
 #include <stdint.h>
 
 namespace mcpd {
@@ -33,68 +34,84 @@ __host__ __device__ constexpr int fmt_row_bytes(int f)
          : (f == FMT_U8_12 || f == FMT_U16_8) ? 16 : 32;
 }
 
-// Per-instance read-only tables in device memory.
-struct DevTables {
-    // Alias table of the site draw: 2^abits columns of capacity
-    // K = 2^(32 - abits); word c = T_c | A_c << (32 - abits), where column c
-    // keeps clone c when the coin (low 32 - abits bits of the site word) is
-    // below T_c and otherwise gives clone A_c.  A column that always keeps
-    // its clone is stored as T_c = 0, A_c = c.
+// Lanes per workgroup; also the stride of the lane-fastest state layout.
+constexpr uint32_t WG_LANES = 256;
+
+enum Place : uint32_t { PLACE_STATE_LDS = 1, PLACE_TABLES_LDS = 2 };
+
+// One instance of a launch, in device memory.  The kernel reads it with
+// scalar loads after a workgroup has taken a ticket for the instance.
+struct InstDesc {
+    // Read-only tables.  Alias table of the site draw: 2^abits columns of
+    // capacity K = 2^(32 - abits); word c = T_c | A_c << (32 - abits), where
+    // column c keeps clone c when the coin (low 32 - abits bits of the site
+    // word) is below T_c and otherwise gives clone A_c.  A column that always
+    // keeps its clone is stored as T_c = 0, A_c = c.
     const uint32_t *alias;
-    const uint32_t *rows;   // [n * row_bytes / 4] clone rows
+    const uint32_t *rows;   // [n * row_bytes / 4] clone rows in the launch's format
     const uint64_t *thr;    // [2^(dmax+1) - 1]: floor(p * 2^53) per ordered free-pool outcome pattern
-    int32_t n, m, dmax, fmt;
-    uint32_t abits;
-    uint32_t row_bytes;
-    uint32_t thr_len;
+    int32_t n, m;
+    uint32_t abits, row_bytes, thr_len;
+    uint32_t words_bits, words_cnt;   // per-lane state words (bit pairs, count pairs)
+    // Run parameters.
+    uint64_t B;             // per-slot horizon
+    uint32_t capmax;        // draws after which an unmet pair stops
+    uint32_t P;             // slots
+    uint32_t k, ell, W;     // window
+    uint32_t cmin;          // max(ell, 1): cost of the cheapest replication
+    uint32_t g;             // instance id in the random-number counter
+    uint32_t hist_width;
+    uint32_t nbuckets;      // rows of S1/S2
+    // Placement in the launch's dynamic LDS (dword offsets).
+    uint32_t place;         // Place bits
+    uint32_t lds_hist, lds_tab;
+    uint32_t tab_off_thr, tab_off_alias, tab_off_rows, tab_bytes;   // within the table block (bytes)
+    // Outputs (zeroed before the launch).
+    int64_t *S1;            // [nbuckets * n]
+    uint64_t *S2;           // [nbuckets * n * 2]
+    uint64_t *hist;         // [hist_bins]
+    uint64_t *stats;        // [ST_COUNT]
+    uint32_t *next_slot;    // slot counter
+    uint32_t *slot_nstar;   // [P] or null
+    uint64_t *slot_units;   // [P] or null
 };
 
-// One launch (one instance).
-struct RunArgs {
-    DevTables T;
-    uint64_t B;         // per-slot horizon
-    uint64_t seed;
-    uint32_t capmax;    // draws after which an unmet pair stops
-    uint32_t P;         // slots
-    uint32_t k, ell, W; // window
-    uint32_t cmin;      // max(ell, 1): cost of the cheapest replication
-    uint32_t g;         // instance id in the random-number counter
+// Arguments of one launch over a batch of instances.
+struct LaunchArgs {
+    const InstDesc *inst;
+    const uint32_t *tickets;    // [nticket]: instance index a workgroup joins
+    uint32_t nticket;
     uint32_t refill;
-    uint32_t ubits;     // u_hi_bits
-    uint32_t hist_bins, hist_width;
-    uint32_t words_bits, words_cnt; // per-lane state words (bit pairs, count pairs)
-    uint32_t list_cap;  // touched-list capacity per lane
-    uint32_t tab_off_thr, tab_off_alias, tab_off_rows, tab_bytes; // LDS table layout (bytes)
-    uint32_t nbuckets;  // rows of S1/S2
-    // per-lane storage (lanes_total = gridDim.x * blockDim.x)
-    int64_t *acc;       // [lanes_total * n] spilled numerators (kept zero between slots)
-    uint32_t *lists;    // [lanes_total * list_cap]
-    uint32_t *gstate;   // [lanes_total * (words_bits + words_cnt)] when state is not in LDS
-    uint64_t *lane_stats; // [lanes_total * ST_COUNT]
-    // outputs
-    int64_t *S1;        // [nbuckets * n]
-    uint64_t *S2;       // [nbuckets * n * 2]
-    uint64_t *hist;     // [hist_bins]
-    uint64_t *stats;    // [ST_COUNT]
-    uint32_t *slot_nstar;  // [P] or null
-    uint64_t *slot_units;  // [P] or null
-    uint32_t *ctrl;     // [0]: next slot, [1]: error flags
+    uint32_t ubits;             // u_hi_bits
+    uint32_t hist_bins;
+    uint32_t list_cap;          // touched-list capacity per lane
+    uint32_t acc_stride;        // >= every n
+    uint32_t gwords;            // >= every global-state instance's words_bits + words_cnt
+    uint32_t pad;
+    const uint64_t *seed;       // device copy of the 64-bit key
+    int64_t *acc;               // [lanes * acc_stride] spilled numerators (kept zero between slots)
+    uint32_t *lists;            // [lanes * list_cap]
+    uint32_t *gstate;           // [lanes * gwords] chain state of global-state instances
+    uint64_t *lane_stats;       // [lanes * ST_COUNT]
+    uint32_t *ctrl;             // [0]: next ticket, [1]: error flags (zeroed before the launch)
 };
 
 enum Stat {
     ST_PROGRESS = 0, ST_RETAINED_UNITS, ST_SINGLE_SITE, ST_REPS_STARTED, ST_REPS_RETAINED,
     ST_REPS_ABORTED, ST_CAP_HITS, ST_ZERO_COMPLETION, ST_TAU_SUM, ST_TAU_MAX, ST_NSTAR_MAX,
-    ST_ROLLBACK_UNITS, ST_COUNT
+    ST_ROLLBACK_UNITS, ST_LIST_OVERFLOWS, ST_COUNT
 };
 
 enum ErrFlag { ERR_BUCKETS = 1 };
 
-// Launch the sampler (defined in mcpd_sampler.hip).  Returns a hipError_t
-// value as int.
-int launch_sampler(const RunArgs &a, int grid, int block, bool lds_state, bool lds_tables,
-                   void *stream);
+// Launch the sampler over a batch (defined in mcpd_sampler.hip); fmt is the
+// row format every instance's rows use.  Returns a hipError_t value as int.
+int launch_sampler(const LaunchArgs &a, int fmt, int grid, size_t lds_bytes, void *stream);
+template <int F>
+int launch_sampler_fmt(const LaunchArgs &a, int grid, size_t lds_bytes, void *stream);
 
-// Bytes of dynamic LDS a launch with this plan uses.
-size_t sampler_lds_bytes(const RunArgs &a, int block, bool lds_state, bool lds_tables);
+// Zero n64 64-bit words at p (a kernel, so that it can sit in a captured
+// graph).  Returns a hipError_t value as int.
+int launch_fill_zero(uint64_t *p, size_t n64, void *stream);
 
 }  // namespace mcpd

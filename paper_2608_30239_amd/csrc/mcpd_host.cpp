@@ -1,5 +1,6 @@
 // Host side of the C ABI (include/mcpd.h): validation, instance tables,
-// launch planning and the final FP64 reduction of the integer buckets.
+// launch planning (placement, tickets, autotuning, graph capture) and the
+// final FP64 reduction of the integer buckets.
 //
 // Instance tables built here, once per instance (the paper computes the
 // score weights "only once, before the chain starts", Section
@@ -9,21 +10,38 @@
 //   * clone rows: pool index | outcome << top bit, ascending
 //   * the decision thresholds floor(p * 2^53) for every ordered pattern of
 //     free-pool outcomes (at most 2^(dmax+1) - 1 values of the FP64 log-odds)
+//
+// Every run, single or batched, is one launch of the persistent sampler over
+// a list of instance descriptors.  Its device work is: copy the key, zero the
+// outputs (a kernel, so that the sequence can be captured in a graph), the
+// sampler, copy the integer outputs back.  The host then divides in extended
+// precision.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <numeric>
 #include <string>
 #include <vector>
 
+// The C ABI is the only thing the library exports.
+#pragma GCC visibility push(default)
 #include "../../include/mcpd.h"
+#pragma GCC visibility pop
 #include "mcpd_device.h"
 
+namespace mcpd {
+namespace host {
+struct Launch;
+}
+}  // namespace mcpd
+
 struct mcpd_instance {
-    int32_t n = 0, m = 0, dmax = 0, fmt = 0, abits = 1;
-    uint32_t row_bytes = 8, thr_len = 1;
+    int32_t n = 0, m = 0, dmax = 0, abits = 1;
+    uint32_t thr_len = 1;
     double fp = 0, fn = 0, q = 0;
     std::vector<int32_t> row_ptr, pool_idx;
     std::vector<uint8_t> y;
@@ -31,29 +49,14 @@ struct mcpd_instance {
     hipStream_t stream = nullptr;
     int device = 0;
     int cus = 0;
-    // device tables
-    uint32_t *d_alias = nullptr, *d_rows = nullptr;
+    uint32_t *d_alias = nullptr;
     uint64_t *d_thr = nullptr;
-    // workspace reused across runs
-    int64_t *d_acc = nullptr;
-    size_t acc_lanes = 0;
-    uint32_t *d_lists = nullptr;
-    uint32_t *d_gstate = nullptr;
-    size_t gstate_words = 0;
-    uint64_t *d_lane_stats = nullptr;
-    size_t lane_stats_cap = 0;
-    int64_t *d_S1 = nullptr;
-    uint64_t *d_S2 = nullptr;
-    size_t bucket_cap = 0, bucket2_cap = 0;
-    uint64_t *d_small = nullptr;   // hist + stats + ctrl
-    size_t small_cap = 0;
-    uint32_t *d_slot_nstar = nullptr;
-    uint64_t *d_slot_units = nullptr;
-    size_t slot_cap = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    uint32_t *d_rows[mcpd::FMT_COUNT] = {};   // clone rows per format, built when first needed
+    mcpd::host::Launch *single = nullptr;      // workspace of mcpd_run_unbiased
 };
 
-namespace {
+namespace mcpd {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -74,15 +77,8 @@ int hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, #expr); \
     } while (0)
 
-constexpr uint32_t LIST_CAP = 64;
-
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// LDS bytes of the table copy: thresholds, alias table, clone rows.
-size_t table_bytes(size_t thr_len, int abits, size_t n, size_t row_bytes)
-{
-    return align16(align16(align16(thr_len * 8) + ((size_t)4 << abits)) + n * row_bytes);
-}
 constexpr size_t LDS_BYTES = 160 * 1024;
 
 int validate_design(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx,
@@ -178,13 +174,24 @@ int quantize(int32_t n, const double *w, std::vector<uint64_t> &mass)
     return MCPD_OK;
 }
 
+int upload_bytes(void **dptr, size_t &cap, const void *h, size_t bytes, hipStream_t s)
+{
+    if (!*dptr || cap != bytes) {
+        if (*dptr) { (void)hipFree(*dptr); *dptr = nullptr; cap = 0; }
+        hipError_t e = hipMalloc(dptr, std::max<size_t>(1, bytes));
+        if (e == hipErrorOutOfMemory) return fail(MCPD_ENOMEM, "device allocation failed");
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        cap = bytes;
+    }
+    if (bytes) HIP_TRY(hipMemcpyAsync(*dptr, h, bytes, hipMemcpyHostToDevice, s));
+    return MCPD_OK;
+}
+
 template <typename T>
 int upload(T **dptr, const std::vector<T> &h, hipStream_t s)
 {
-    if (*dptr) { (void)hipFree(*dptr); *dptr = nullptr; }
-    HIP_TRY(hipMalloc(reinterpret_cast<void **>(dptr), std::max<size_t>(1, h.size()) * sizeof(T)));
-    if (!h.empty()) HIP_TRY(hipMemcpyAsync(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return MCPD_OK;
+    size_t cap = *dptr ? h.size() * sizeof(T) : 0;   // tables keep their size for the instance's life
+    return upload_bytes(reinterpret_cast<void **>(dptr), cap, h.data(), h.size() * sizeof(T), s);
 }
 
 // Alias table of the site draw from the integer masses (Walker's method,
@@ -235,16 +242,6 @@ void free_ptr(void *p)
     if (p) (void)hipFree(p);
 }
 
-void release(mcpd_instance *I)
-{
-    free_ptr(I->d_alias); free_ptr(I->d_rows); free_ptr(I->d_thr); free_ptr(I->d_lane_stats);
-    free_ptr(I->d_acc); free_ptr(I->d_lists); free_ptr(I->d_gstate);
-    free_ptr(I->d_S1); free_ptr(I->d_S2); free_ptr(I->d_small);
-    free_ptr(I->d_slot_nstar); free_ptr(I->d_slot_units);
-    if (I->ev0) (void)hipEventDestroy(I->ev0);
-    if (I->ev1) (void)hipEventDestroy(I->ev1);
-}
-
 template <typename T>
 int ensure(T **p, size_t &cap, size_t want)
 {
@@ -259,7 +256,534 @@ int ensure(T **p, size_t &cap, size_t want)
     return MCPD_OK;
 }
 
-}  // namespace
+// Narrowest row format with at least `need` entries.
+int pick_format(bool wide, int need)
+{
+    if (!wide) return need <= 4 ? FMT_U8_4 : need <= 5 ? FMT_U8_5 : need <= 8 ? FMT_U8_8 : FMT_U8_12;
+    return need <= 4 ? FMT_U16_4 : need <= 8 ? FMT_U16_8 : FMT_U16_12;
+}
+
+// Clone rows of an instance in format fmt (entry = pool | outcome << top
+// bit, ascending, padded with all-ones), uploaded on first use.
+int rows_for(mcpd_instance *I, int fmt, const uint32_t **out)
+{
+    if (!I->d_rows[fmt]) {
+        const size_t rb = (size_t)fmt_row_bytes(fmt);
+        std::vector<uint8_t> rowb((size_t)I->n * rb, 0xFFu);
+        for (int32_t i = 0; i < I->n; ++i) {
+            for (int32_t e = I->row_ptr[i]; e < I->row_ptr[i + 1]; ++e) {
+                const uint32_t j = (uint32_t)I->pool_idx[e], yj = I->y[j];
+                const size_t at = (size_t)i * rb;
+                const int32_t pos = e - I->row_ptr[i];
+                if (!fmt_wide(fmt)) {
+                    rowb[at + pos] = (uint8_t)(j | (yj << 7));
+                } else {
+                    const uint16_t v = (uint16_t)(j | (yj << 15));
+                    std::memcpy(&rowb[at + 2 * pos], &v, 2);
+                }
+            }
+        }
+        std::vector<uint32_t> rows(rowb.size() / 4);
+        std::memcpy(rows.data(), rowb.data(), rowb.size());
+        int rc = upload(&I->d_rows[fmt], rows, I->stream);
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(I->stream));
+    }
+    *out = I->d_rows[fmt];
+    return MCPD_OK;
+}
+
+struct Item {
+    mcpd_instance *I;
+    uint64_t budget;
+    uint32_t slots, k, m;
+};
+
+// Tuning knobs of a launch (results never depend on them).
+struct Config {
+    uint32_t wg_per_cu = 1;   // workgroups of 256 lanes per compute unit
+    uint32_t spl = 1;         // slots per lane one ticket stands for
+};
+
+// Placement of one instance in a workgroup's LDS of `budget` bytes.
+struct Layout {
+    uint32_t words_bits, words_cnt, place, lds_hist, lds_tab;
+    uint32_t off_thr, off_alias, off_rows, tab_bytes;
+    size_t used;
+};
+
+int layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan, Layout &L)
+{
+    L.words_bits = (uint32_t)((I->n + 15) / 16);
+    L.words_cnt = (uint32_t)((I->m + 1) / 2);
+    const size_t state = ((size_t)L.words_bits + L.words_cnt) * WG_LANES * 4u;
+    const size_t hist = align16((size_t)hist_bins * 4u);
+    L.off_thr = 0;
+    L.off_alias = (uint32_t)align16((size_t)I->thr_len * 8u);
+    L.off_rows = (uint32_t)align16((size_t)L.off_alias + ((size_t)4 << I->abits));
+    const size_t tab = align16((size_t)L.off_rows + (size_t)I->n * fmt_row_bytes(fmt));
+    L.tab_bytes = (uint32_t)std::min<size_t>(tab, 0xFFFFFFFFu);
+    if (hist > budget) return fail(MCPD_EINVAL, "hist_bins too large for LDS");
+    bool sl, tl;
+    if (plan == 0) {
+        sl = tl = true;
+        if (state + hist + tab > budget) {
+            tl = false;
+            if (state + hist > budget) { sl = false; tl = hist + tab <= budget; }
+        }
+    } else {
+        sl = plan <= 2;
+        tl = plan == 1 || plan == 3;
+        if ((sl ? state : 0) + hist + (tl ? tab : 0) > budget)
+            return fail(MCPD_EINVAL, "requested plan does not fit in LDS");
+    }
+    L.place = (sl ? PLACE_STATE_LDS : 0u) | (tl ? PLACE_TABLES_LDS : 0u);
+    L.lds_hist = sl ? (uint32_t)(state / 4) : 0u;
+    L.lds_tab = L.lds_hist + (uint32_t)(hist / 4);
+    L.used = (size_t)L.lds_tab * 4 + (tl ? tab : 0);
+    return MCPD_OK;
+}
+
+// Words of one instance's block of outputs: slot counter, statistics,
+// histogram, S1, S2.
+size_t block_words(size_t n, size_t nb, uint32_t hist_bins)
+{
+    return 1 + ST_COUNT + hist_bins + nb * n + 2 * nb * n;
+}
+
+struct Launch {
+    // inputs
+    std::vector<Item> items;
+    mcpd_run_opts opts{};
+    bool batch_ids = false;    // instance i uses g = instance_id + i
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0, cus = 0;
+    // plan
+    Config cfg;
+    int fmt = 0;
+    int grid = 0;
+    size_t lds = 0;
+    uint32_t acc_stride = 1, gwords = 0, list_cap = 64;
+    std::vector<InstDesc> desc;
+    std::vector<uint32_t> tickets;
+    std::vector<size_t> off;       // word offset of each item's output block
+    std::vector<uint32_t> nb;      // bucket rows per item
+    std::vector<size_t> slot_off;  // offset of each item's slot records
+    size_t zero_words = 0, slot_total = 0;
+    bool slot_records = false;
+    // device workspace
+    InstDesc *d_desc = nullptr; size_t desc_cap = 0;
+    uint32_t *d_tickets = nullptr; size_t tickets_cap = 0;
+    uint64_t *d_zero = nullptr; size_t zero_cap = 0;
+    uint64_t *d_seed = nullptr; size_t seed_cap = 0;
+    int64_t *d_acc = nullptr; size_t acc_cap = 0;
+    uint32_t *d_lists = nullptr; size_t lists_cap = 0;
+    uint32_t *d_gstate = nullptr; size_t gstate_cap = 0;
+    uint64_t *d_lane_stats = nullptr; size_t ls_cap = 0;
+    uint32_t *d_slot_nstar = nullptr; size_t sn_cap = 0;
+    uint64_t *d_slot_units = nullptr; size_t su_cap = 0;
+    // pinned host staging
+    uint64_t *h_seed = nullptr;
+    uint64_t *h_out = nullptr; size_t h_out_cap = 0;
+    // graph and timing
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    float last_ms = 0.f;
+
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~Launch()
+    {
+        (void)hipStreamSynchronize(stream);
+        drop_graph();
+        free_ptr(d_desc); free_ptr(d_tickets); free_ptr(d_zero); free_ptr(d_seed); free_ptr(d_acc);
+        free_ptr(d_lists); free_ptr(d_gstate); free_ptr(d_lane_stats); free_ptr(d_slot_nstar);
+        free_ptr(d_slot_units);
+        if (h_seed) (void)hipHostFree(h_seed);
+        if (h_out) (void)hipHostFree(h_out);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+// Check the run parameters of every item against the options.
+int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool batch_ids)
+{
+    if (o.hist_bins == 0) return fail(MCPD_EINVAL, "hist_bins must be >= 1");
+    if (o.u_hi_bits < 1 || o.u_hi_bits > 32) return fail(MCPD_EINVAL, "u_hi_bits must be in 1..32");
+    if (o.plan > 4) return fail(MCPD_EINVAL, "plan must be 0..4");
+    if (o.wg_per_cu > 8) return fail(MCPD_EINVAL, "wg_per_cu must be 0..8");
+    const uint64_t last_id = (uint64_t)o.instance_id + (batch_ids ? items.size() - 1 : 0);
+    if (last_id >= (1u << 24)) return fail(MCPD_EINVAL, "instance ids must be < 2^24");
+    for (const Item &it : items) {
+        if (!it.I) return fail(MCPD_EINVAL, "null instance");
+        if (it.slots == 0) return fail(MCPD_EINVAL, "slots must be >= 1");
+        if (it.k > it.m || it.m > (1u << 31)) return fail(MCPD_EINVAL, "need 0 <= k <= m <= 2^31");
+        const uint32_t cmin = std::max<uint32_t>(it.m, 1u);
+        if (o.max_steps && (o.max_steps < cmin || o.max_steps > 0xFFFFFFFFull))
+            return fail(MCPD_EINVAL, "max_steps must be 0 or in [max(m,1), 2^32-1]");
+        const uint64_t B = it.budget / it.slots;
+        const uint64_t nb = std::max<uint64_t>(1, B / cmin);
+        if (nb * (uint64_t)it.I->n > (1ull << 27)) return fail(MCPD_EINVAL, "budget/slots/m give too many N* buckets");
+    }
+    return MCPD_OK;
+}
+
+// The default configuration: one workgroup per CU when most of the work
+// keeps its chain state in LDS (that already takes the LDS), otherwise as
+// many as the registers allow (more waves hide the latency of global
+// state).
+Config default_config(const Launch &L)
+{
+    Config c;
+    double in_lds = 0, total = 0;
+    for (const Item &it : L.items) {
+        Layout lay;
+        if (layout(it.I, L.fmt, L.opts.hist_bins, LDS_BYTES - 1024, 0, lay)) continue;
+        const double w = (double)it.budget + (double)it.slots;
+        total += w;
+        if (lay.place & PLACE_STATE_LDS) in_lds += w;
+    }
+    c.wg_per_cu = (total > 0 && in_lds >= 0.5 * total) ? 1u : 2u;
+    if (L.opts.wg_per_cu) c.wg_per_cu = L.opts.wg_per_cu;
+    c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 1u;
+    return c;
+}
+
+// Plan a launch for configuration c and make its workspace fit.
+int plan(Launch &L, const Config &c)
+{
+    const mcpd_run_opts &o = L.opts;
+    L.cfg = c;
+    L.drop_graph();
+    // the kernel's own few bytes of static LDS come out of the same 160 KiB
+    const size_t budget = (LDS_BYTES / c.wg_per_cu - 1024) & ~(size_t)1023;
+    const size_t count = L.items.size();
+    L.desc.assign(count, InstDesc{});
+    L.off.assign(count, 0);
+    L.nb.assign(count, 0);
+    L.slot_off.assign(count, 0);
+    L.lds = 0;
+    L.acc_stride = 1;
+    L.gwords = 0;
+    size_t words = 1;   // word 0: ticket counter and error flags
+    size_t slots_total = 0;
+    for (size_t i = 0; i < count; ++i) {
+        const Item &it = L.items[i];
+        mcpd_instance *I = it.I;
+        Layout lay;
+        int rc = layout(I, L.fmt, o.hist_bins, budget, o.plan, lay);
+        if (rc) return rc;
+        const uint32_t *rows = nullptr;
+        if ((rc = rows_for(I, L.fmt, &rows))) return rc;
+        InstDesc &d = L.desc[i];
+        d.alias = I->d_alias;
+        d.rows = rows;
+        d.thr = I->d_thr;
+        d.n = I->n;
+        d.m = I->m;
+        d.abits = (uint32_t)I->abits;
+        d.row_bytes = (uint32_t)fmt_row_bytes(L.fmt);
+        d.thr_len = I->thr_len;
+        d.words_bits = lay.words_bits;
+        d.words_cnt = lay.words_cnt;
+        d.B = it.budget / it.slots;
+        d.cmin = std::max<uint32_t>(it.m, 1u);
+        d.capmax = o.max_steps ? (uint32_t)std::max<uint64_t>(o.max_steps, it.m) : 0xFFFFFFFFu;
+        d.P = it.slots;
+        d.k = it.k;
+        d.ell = it.m;
+        d.W = it.m - it.k + 1;
+        d.g = o.instance_id + (L.batch_ids ? (uint32_t)i : 0u);
+        d.hist_width = o.hist_width ? o.hist_width : (uint32_t)I->n;
+        d.nbuckets = (uint32_t)std::max<uint64_t>(1, d.B / d.cmin);
+        d.place = lay.place;
+        d.lds_hist = lay.lds_hist;
+        d.lds_tab = lay.lds_tab;
+        d.tab_off_thr = lay.off_thr;
+        d.tab_off_alias = lay.off_alias;
+        d.tab_off_rows = lay.off_rows;
+        d.tab_bytes = lay.tab_bytes;
+        L.lds = std::max(L.lds, lay.used);
+        if (!(lay.place & PLACE_STATE_LDS))
+            L.gwords = std::max<uint32_t>(L.gwords, lay.words_bits + lay.words_cnt);
+        L.acc_stride = std::max<uint32_t>(L.acc_stride, (uint32_t)I->n);
+        L.nb[i] = d.nbuckets;
+        L.off[i] = words;
+        words += block_words((size_t)I->n, d.nbuckets, o.hist_bins);
+        L.slot_off[i] = slots_total;
+        slots_total += it.slots;
+    }
+    L.zero_words = words;
+    L.slot_total = slots_total;
+
+    // Tickets: longest slots first, each instance split into tickets of
+    // 256 * spl slots.
+    std::vector<size_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return L.desc[a].B > L.desc[b].B; });
+    L.tickets.clear();
+    const uint64_t per_ticket = (uint64_t)WG_LANES * c.spl;
+    for (size_t i : order) {
+        const uint64_t t = std::max<uint64_t>(1, (L.desc[i].P + per_ticket - 1) / per_ticket);
+        for (uint64_t j = 0; j < t; ++j) L.tickets.push_back((uint32_t)i);
+    }
+    L.grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.cus * c.wg_per_cu, L.tickets.size()));
+    const size_t lanes = (size_t)L.grid * WG_LANES;
+    L.list_cap = std::min<uint32_t>(512, std::max<uint32_t>(64, L.acc_stride / 16));
+
+    // Workspace.  Numerator rows stay zero between runs (the kernel clears
+    // what it used), so they are cleared only when (re)allocated.
+    int rc;
+    const size_t acc_words = lanes * (size_t)L.acc_stride;
+    if (acc_words > ((size_t)8 << 30)) return fail(MCPD_ENOMEM, "numerator workspace above 64 GiB; use fewer workgroups per CU");
+    if (L.acc_cap < acc_words || !L.d_acc) {
+        if ((rc = ensure(&L.d_acc, L.acc_cap, acc_words))) return rc;
+        int e = launch_fill_zero(reinterpret_cast<uint64_t *>(L.d_acc), L.acc_cap, L.stream);
+        if (e != hipSuccess) return hip_fail((hipError_t)e, "zero numerators");
+    }
+    if ((rc = ensure(&L.d_lists, L.lists_cap, lanes * L.list_cap))) return rc;
+    if (L.gwords && (rc = ensure(&L.d_gstate, L.gstate_cap, lanes * (size_t)L.gwords))) return rc;
+    if ((rc = ensure(&L.d_lane_stats, L.ls_cap, lanes * (size_t)ST_COUNT))) return rc;
+    if ((rc = ensure(&L.d_zero, L.zero_cap, L.zero_words))) return rc;
+    if ((rc = ensure(&L.d_seed, L.seed_cap, (size_t)1))) return rc;
+    if (L.slot_records) {
+        if ((rc = ensure(&L.d_slot_nstar, L.sn_cap, slots_total))) return rc;
+        if ((rc = ensure(&L.d_slot_units, L.su_cap, slots_total))) return rc;
+    }
+    if (L.h_out_cap < L.zero_words) {
+        if (L.h_out) (void)hipHostFree(L.h_out);
+        L.h_out = nullptr;
+        L.h_out_cap = 0;
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&L.h_out), L.zero_words * 8, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+        L.h_out_cap = L.zero_words;
+    }
+    if (!L.h_seed) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&L.h_seed), 8, hipHostMallocDefault));
+    if (!L.ev0) HIP_TRY(hipEventCreate(&L.ev0));
+    if (!L.ev1) HIP_TRY(hipEventCreate(&L.ev1));
+    for (size_t i = 0; i < count; ++i) {
+        InstDesc &d = L.desc[i];
+        uint64_t *blk = L.d_zero + L.off[i];
+        d.next_slot = reinterpret_cast<uint32_t *>(blk);
+        d.stats = blk + 1;
+        d.hist = blk + 1 + ST_COUNT;
+        d.S1 = reinterpret_cast<int64_t *>(blk + 1 + ST_COUNT + o.hist_bins);
+        d.S2 = blk + 1 + ST_COUNT + o.hist_bins + (size_t)d.nbuckets * d.n;
+        d.slot_nstar = L.slot_records ? L.d_slot_nstar + L.slot_off[i] : nullptr;
+        d.slot_units = L.slot_records ? L.d_slot_units + L.slot_off[i] : nullptr;
+    }
+    void *dd = L.d_desc, *dt = L.d_tickets;
+    if ((rc = upload_bytes(&dd, L.desc_cap, L.desc.data(), L.desc.size() * sizeof(InstDesc), L.stream))) return rc;
+    L.d_desc = reinterpret_cast<InstDesc *>(dd);
+    if ((rc = upload_bytes(&dt, L.tickets_cap, L.tickets.data(), L.tickets.size() * 4, L.stream))) return rc;
+    L.d_tickets = reinterpret_cast<uint32_t *>(dt);
+    HIP_TRY(hipStreamSynchronize(L.stream));
+    return MCPD_OK;
+}
+
+LaunchArgs launch_args(const Launch &L)
+{
+    LaunchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.inst = L.d_desc;
+    a.tickets = L.d_tickets;
+    a.nticket = (uint32_t)L.tickets.size();
+    a.refill = L.opts.refill ? 1u : 0u;
+    a.ubits = L.opts.u_hi_bits;
+    a.hist_bins = L.opts.hist_bins;
+    a.list_cap = L.list_cap;
+    a.acc_stride = L.acc_stride;
+    a.gwords = L.gwords;
+    a.seed = L.d_seed;
+    a.acc = L.d_acc;
+    a.lists = L.d_lists;
+    a.gstate = L.gwords ? L.d_gstate : nullptr;
+    a.lane_stats = L.d_lane_stats;
+    a.ctrl = reinterpret_cast<uint32_t *>(L.d_zero);
+    return a;
+}
+
+// The device work of one run: key, zeroing, sampler, copy back.  With
+// `timed`, events bracket the sampler alone.
+int enqueue(Launch &L, bool timed)
+{
+    HIP_TRY(hipMemcpyAsync(L.d_seed, L.h_seed, 8, hipMemcpyHostToDevice, L.stream));
+    int e = launch_fill_zero(L.d_zero, L.zero_words, L.stream);
+    if (e != hipSuccess) return hip_fail((hipError_t)e, "zero outputs");
+    if (timed) HIP_TRY(hipEventRecord(L.ev0, L.stream));
+    e = launch_sampler(launch_args(L), L.fmt, L.grid, L.lds, L.stream);
+    if (e != hipSuccess) return hip_fail((hipError_t)e, "sampler launch");
+    if (timed) HIP_TRY(hipEventRecord(L.ev1, L.stream));
+    HIP_TRY(hipMemcpyAsync(L.h_out, L.d_zero, L.zero_words * 8, hipMemcpyDeviceToHost, L.stream));
+    return MCPD_OK;
+}
+
+int capture(Launch &L)
+{
+    L.drop_graph();
+    HIP_TRY(hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue(L, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(L.stream, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    L.graph = g;
+    e = hipGraphInstantiate(&L.exec, L.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { L.drop_graph(); return hip_fail(e, "hipGraphInstantiate"); }
+    return MCPD_OK;
+}
+
+// One run.  With a graph, the events bracket the whole replay (key copy,
+// zeroing, sampler, copy back); without, the sampler alone.
+int execute(Launch &L, uint64_t seed, bool use_graph)
+{
+    *L.h_seed = seed;
+    int rc;
+    if (use_graph) {
+        if (!L.exec && (rc = capture(L))) return rc;
+        HIP_TRY(hipEventRecord(L.ev0, L.stream));
+        HIP_TRY(hipGraphLaunch(L.exec, L.stream));
+        HIP_TRY(hipEventRecord(L.ev1, L.stream));
+    } else if ((rc = enqueue(L, true))) {
+        return rc;
+    }
+    HIP_TRY(hipStreamSynchronize(L.stream));
+    HIP_TRY(hipEventElapsedTime(&L.last_ms, L.ev0, L.ev1));
+    const uint32_t flags = (uint32_t)(L.h_out[0] >> 32);
+    if (flags & ERR_BUCKETS) return fail(MCPD_EINVAL, "internal: N* above bucket count");
+    return MCPD_OK;
+}
+
+// Marginals, standard errors, histogram and statistics of item i from the
+// copied-back integers:
+//   marginal_j = (1/(P W)) sum_n S1[n][j] / n,  SE from the sums of squares.
+int finish_item(const Launch &L, size_t i, double *marginals, double *stderr_out, uint64_t *hist,
+                mcpd_run_stats *stats)
+{
+    const InstDesc &d = L.desc[i];
+    const size_t n = (size_t)d.n;
+    const uint32_t nb = L.nb[i];
+    const uint64_t *blk = L.h_out + L.off[i];
+    const uint64_t *st = blk + 1;
+    const uint64_t *h = blk + 1 + ST_COUNT;
+    const int64_t *S1 = reinterpret_cast<const int64_t *>(h + L.opts.hist_bins);
+    const uint64_t *S2 = h + L.opts.hist_bins + (size_t)nb * n;
+    const uint32_t slots = d.P;
+    const long double PW = (long double)slots * (long double)d.W;
+    const long double W = (long double)d.W;
+    if (marginals || stderr_out) {
+        for (size_t j = 0; j < n; ++j) {
+            long double sa = 0.0L, sq = 0.0L;
+            for (uint32_t r = 0; r < nb; ++r) {
+                const size_t idx = (size_t)r * n + j;
+                const long double nn = (long double)(r + 1);
+                sa += (long double)S1[idx] / nn;
+                const long double v2 =
+                    (long double)S2[2 * idx + 1] * 18446744073709551616.0L + (long double)S2[2 * idx];
+                sq += v2 / (nn * nn);
+            }
+            if (marginals) marginals[j] = (double)(sa / PW);
+            if (stderr_out) {
+                if (slots > 1) {
+                    const long double sumA = sa / W, sumA2 = sq / (W * W);
+                    long double var = (sumA2 - sumA * sumA / (long double)slots) / (long double)(slots - 1);
+                    if (var < 0) var = 0;
+                    stderr_out[j] = (double)std::sqrt(var / (long double)slots);
+                } else {
+                    stderr_out[j] = NAN;
+                }
+            }
+        }
+    }
+    if (hist) std::memcpy(hist, h, sizeof(uint64_t) * L.opts.hist_bins);
+    if (stats) {
+        stats->progress_units = st[ST_PROGRESS];
+        stats->retained_units = st[ST_RETAINED_UNITS];
+        stats->single_site_updates = st[ST_SINGLE_SITE];
+        stats->reps_started = st[ST_REPS_STARTED];
+        stats->reps_retained = st[ST_REPS_RETAINED];
+        stats->reps_aborted = st[ST_REPS_ABORTED];
+        stats->cap_hits = st[ST_CAP_HITS];
+        stats->zero_completion_slots = st[ST_ZERO_COMPLETION];
+        stats->tau_sum = st[ST_TAU_SUM];
+        stats->tau_max = st[ST_TAU_MAX];
+        stats->nstar_max = st[ST_NSTAR_MAX];
+        stats->rollback_units = st[ST_ROLLBACK_UNITS];
+        stats->list_overflows = st[ST_LIST_OVERFLOWS];
+        stats->lanes = (uint64_t)L.grid * WG_LANES;
+        stats->placement = d.place;
+        stats->wg_per_cu = L.cfg.wg_per_cu;
+        stats->kernel_ms = L.last_ms;
+    }
+    if (L.opts.strict_cap && st[ST_CAP_HITS]) return fail(MCPD_ECAP, "a retained pair hit the meeting cap");
+    return MCPD_OK;
+}
+
+// Integer bucket sums of item i (rows beyond its bucket count are zero).
+int copy_buckets(const Launch &L, size_t i, uint32_t rows, int64_t *sum, uint64_t *sumsq)
+{
+    const InstDesc &d = L.desc[i];
+    const size_t n = (size_t)d.n;
+    const uint32_t nb = L.nb[i];
+    const uint64_t *blk = L.h_out + L.off[i];
+    if (blk[1 + ST_NSTAR_MAX] > rows) return fail(MCPD_EINVAL, "bucket_rows below N*");
+    const uint64_t *h = blk + 1 + ST_COUNT;
+    const size_t r = std::min<size_t>(rows, nb);
+    if (sum) {
+        std::memset(sum, 0, sizeof(int64_t) * (size_t)rows * n);
+        std::memcpy(sum, h + L.opts.hist_bins, sizeof(int64_t) * r * n);
+    }
+    if (sumsq) {
+        std::memset(sumsq, 0, sizeof(uint64_t) * 2 * (size_t)rows * n);
+        std::memcpy(sumsq, h + L.opts.hist_bins + (size_t)nb * n, sizeof(uint64_t) * 2 * r * n);
+    }
+    return MCPD_OK;
+}
+
+int copy_slot_records(Launch &L, size_t i, uint32_t *nstar, uint64_t *units)
+{
+    if (!L.slot_records) return fail(MCPD_EINVAL, "slot records were not kept (keep_slot_records = 0)");
+    const size_t P = L.desc[i].P;
+    if (nstar)
+        HIP_TRY(hipMemcpyAsync(nstar, L.d_slot_nstar + L.slot_off[i], P * 4, hipMemcpyDeviceToHost, L.stream));
+    if (units)
+        HIP_TRY(hipMemcpyAsync(units, L.d_slot_units + L.slot_off[i], P * 8, hipMemcpyDeviceToHost, L.stream));
+    HIP_TRY(hipStreamSynchronize(L.stream));
+    return MCPD_OK;
+}
+
+void release(mcpd_instance *I)
+{
+    if (I->single) { delete I->single; I->single = nullptr; }
+    if (I->d_alias) (void)hipFree(I->d_alias);
+    if (I->d_thr) (void)hipFree(I->d_thr);
+    for (uint32_t *&p : I->d_rows) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    }
+    I->d_alias = nullptr;
+    I->d_thr = nullptr;
+}
+
+}  // namespace host
+}  // namespace mcpd
+
+using mcpd::host::Launch;
+using mcpd::host::Item;
+using mcpd::host::Config;
+
+struct mcpd_batch {
+    std::unique_ptr<Launch> L;
+};
 
 extern "C" {
 
@@ -271,6 +795,7 @@ void mcpd_run_opts_init(mcpd_run_opts *o)
     o->hist_bins = 64;
     o->hist_width = 0;
     o->u_hi_bits = 32;
+    o->use_graph = 1;
 }
 
 const char *mcpd_strerror(int code)
@@ -285,11 +810,12 @@ const char *mcpd_strerror(int code)
     }
 }
 
-const char *mcpd_last_error(void) { return g_last_error.c_str(); }
+const char *mcpd_last_error(void) { return mcpd::host::g_last_error.c_str(); }
 
 int mcpd_score_weights(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx,
                        const uint8_t *y, double fp, double fn, double q, double *s_out, double *w_out)
 {
+    using namespace mcpd::host;
     int rc = validate_design(n, m, row_ptr, pool_idx, y, fp, fn, q, nullptr);
     if (rc) return rc;
     if (!w_out) return fail(MCPD_EINVAL, "w_out is null");
@@ -302,21 +828,15 @@ int mcpd_score_weights(int32_t n, int32_t m, const int32_t *row_ptr, const int32
 int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx,
                 const uint8_t *y, double fp, double fn, double q, void *hip_stream, mcpd_instance **out)
 {
+    using namespace mcpd::host;
     if (!out) return fail(MCPD_EINVAL, "out is null");
     *out = nullptr;
     int32_t dmax = 0;
     int rc = validate_design(n, m, row_ptr, pool_idx, y, fp, fn, q, &dmax);
     if (rc) return rc;
-    mcpd_instance *I = new (std::nothrow) mcpd_instance();
+    std::unique_ptr<mcpd_instance> I(new (std::nothrow) mcpd_instance());
     if (!I) return fail(MCPD_ENOMEM, "host allocation failed");
     I->n = n; I->m = m; I->dmax = dmax; I->fp = fp; I->fn = fn; I->q = q;
-    // record format: narrowest entries, shortest compile-time loop >= dmax
-    if (m <= 127) {
-        I->fmt = dmax <= 4 ? mcpd::FMT_U8_4 : dmax <= 5 ? mcpd::FMT_U8_5 : dmax <= 8 ? mcpd::FMT_U8_8 : mcpd::FMT_U8_12;
-    } else {
-        I->fmt = dmax <= 4 ? mcpd::FMT_U16_4 : dmax <= 8 ? mcpd::FMT_U16_8 : mcpd::FMT_U16_12;
-    }
-    I->row_bytes = (uint32_t)mcpd::fmt_row_bytes(I->fmt);
     int ab = 1;
     while ((1 << ab) < n) ++ab;
     I->abits = ab;
@@ -328,26 +848,7 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     // weights -> masses (host only; no device needed yet)
     std::vector<double> s(n), w(n);
     score_weights(n, m, row_ptr, pool_idx, y, fp, fn, q, s.data(), w.data());
-    rc = quantize(n, w.data(), I->mass);
-    if (rc) { delete I; return rc; }
-
-    // rows: entry = pool | outcome << (top bit), ascending, padded with all-ones
-    std::vector<uint8_t> rowb((size_t)n * I->row_bytes, 0xFFu);
-    for (int32_t i = 0; i < n; ++i) {
-        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-            const uint32_t j = (uint32_t)pool_idx[e], yj = y[pool_idx[e]];
-            const size_t at = (size_t)i * I->row_bytes;
-            const int32_t pos = e - row_ptr[i];
-            if (!mcpd::fmt_wide(I->fmt)) {
-                rowb[at + pos] = (uint8_t)(j | (yj << 7));
-            } else {
-                const uint16_t v = (uint16_t)(j | (yj << 15));
-                std::memcpy(&rowb[at + 2 * pos], &v, 2);
-            }
-        }
-    }
-    std::vector<uint32_t> rows(rowb.size() / 4);
-    std::memcpy(rows.data(), rowb.data(), rowb.size());
+    if ((rc = quantize(n, w.data(), I->mass))) return rc;
 
     // thresholds for every ordered pattern of free-pool outcomes: the FP64
     // sum lq + a_{1st} + a_{2nd} + ... in ascending pool order
@@ -368,28 +869,24 @@ int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *poo
     }
 
     hipError_t e = hipGetDevice(&I->device);
-    if (e != hipSuccess) { delete I; return hip_fail(e, "hipGetDevice"); }
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     e = hipDeviceGetAttribute(&I->cus, hipDeviceAttributeMultiprocessorCount, I->device);
-    if (e != hipSuccess) { delete I; return hip_fail(e, "hipDeviceGetAttribute"); }
-    if ((rc = upload(&I->d_thr, thr, I->stream)) || (rc = upload(&I->d_rows, rows, I->stream)) ||
-        (rc = upload_site_tables(I))) {
-        release(I);
-        delete I;
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    const uint32_t *rows = nullptr;
+    if ((rc = upload(&I->d_thr, thr, I->stream)) || (rc = upload_site_tables(I.get())) ||
+        (rc = rows_for(I.get(), pick_format(m > 127, dmax), &rows))) {
+        release(I.get());
         return rc;
     }
-    if ((e = hipEventCreate(&I->ev0)) != hipSuccess || (e = hipEventCreate(&I->ev1)) != hipSuccess) {
-        release(I);
-        delete I;
-        return hip_fail(e, "hipEventCreate");
-    }
     e = hipStreamSynchronize(I->stream);
-    if (e != hipSuccess) { release(I); delete I; return hip_fail(e, "hipStreamSynchronize"); }
-    *out = I;
+    if (e != hipSuccess) { release(I.get()); return hip_fail(e, "hipStreamSynchronize"); }
+    *out = I.release();
     return MCPD_OK;
 }
 
 int mcpd_set_weights(mcpd_instance *I, const double *w)
 {
+    using namespace mcpd::host;
     if (!I) return fail(MCPD_EINVAL, "null instance");
     std::vector<uint64_t> mass;
     int rc;
@@ -403,14 +900,14 @@ int mcpd_set_weights(mcpd_instance *I, const double *w)
     }
     if (rc) return rc;
     I->mass.swap(mass);
-    rc = upload_site_tables(I);
-    if (rc) return rc;
+    if ((rc = upload_site_tables(I))) return rc;
     HIP_TRY(hipStreamSynchronize(I->stream));
     return MCPD_OK;
 }
 
 int mcpd_get_weights(const mcpd_instance *I, double *w_exact, uint64_t *mass)
 {
+    using namespace mcpd::host;
     if (!I) return fail(MCPD_EINVAL, "null instance");
     for (int32_t i = 0; i < I->n; ++i) {
         if (w_exact) w_exact[i] = (double)I->mass[i] / 4294967296.0;
@@ -423,225 +920,193 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
                       uint64_t seed, const mcpd_run_opts *opts_in, double *marginals, double *stderr_out,
                       uint64_t *hist, mcpd_run_stats *stats)
 {
+    using namespace mcpd::host;
     if (!I) return fail(MCPD_EINVAL, "null instance");
     if (!marginals || !stderr_out) return fail(MCPD_EINVAL, "null output");
     mcpd_run_opts opts;
     if (opts_in) opts = *opts_in; else mcpd_run_opts_init(&opts);
-    if (slots == 0) return fail(MCPD_EINVAL, "slots must be >= 1");
-    if (k > m || m > (1u << 31)) return fail(MCPD_EINVAL, "need 0 <= k <= m <= 2^31");
-    if (opts.hist_bins == 0) return fail(MCPD_EINVAL, "hist_bins must be >= 1");
-    if (opts.u_hi_bits < 1 || opts.u_hi_bits > 32) return fail(MCPD_EINVAL, "u_hi_bits must be in 1..32");
-    if (opts.instance_id >= (1u << 24)) return fail(MCPD_EINVAL, "instance_id must be < 2^24");
-    const uint32_t cmin = std::max<uint32_t>(m, 1u);
-    if (opts.max_steps && (opts.max_steps < cmin || opts.max_steps > 0xFFFFFFFFull))
-        return fail(MCPD_EINVAL, "max_steps must be 0 or in [max(m,1), 2^32-1]");
-    const int32_t n = I->n;
-    const uint64_t B = budget / slots;
-    const uint64_t nb64 = std::max<uint64_t>(1, B / cmin);
-    if (nb64 * (uint64_t)n > (1ull << 27)) return fail(MCPD_EINVAL, "budget/slots/m give too many N* buckets");
-    const uint32_t nbuckets = (uint32_t)nb64;
-
-    mcpd::RunArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.T.alias = I->d_alias; a.T.rows = I->d_rows; a.T.thr = I->d_thr;
-    a.T.n = n; a.T.m = I->m; a.T.dmax = I->dmax; a.T.fmt = I->fmt;
-    a.T.abits = (uint32_t)I->abits;
-    a.T.row_bytes = I->row_bytes;
-    a.T.thr_len = I->thr_len;
-    a.B = B;
-    a.capmax = opts.max_steps ? (uint32_t)std::max<uint64_t>(opts.max_steps, m) : 0xFFFFFFFFu;
-    a.seed = seed;
-    a.P = slots;
-    a.k = k; a.ell = m; a.W = m - k + 1; a.cmin = cmin;
-    a.g = opts.instance_id;
-    a.refill = opts.refill ? 1u : 0u;
-    a.ubits = opts.u_hi_bits;
-    a.hist_bins = opts.hist_bins;
-    a.hist_width = opts.hist_width ? opts.hist_width : (uint32_t)n;
-    a.words_bits = (uint32_t)((n + 15) / 16);
-    a.words_cnt = (uint32_t)((I->m + 1) / 2);
-    a.list_cap = LIST_CAP;
-    a.nbuckets = nbuckets;
-
-    // LDS copy of the read-only tables: thresholds, alias table, clone rows.
-    a.tab_off_thr = 0;
-    a.tab_off_alias = (uint32_t)align16((size_t)I->thr_len * 8);
-    a.tab_off_rows = (uint32_t)align16(a.tab_off_alias + ((size_t)4 << I->abits));
-    const size_t tab_bytes = table_bytes(I->thr_len, I->abits, n, I->row_bytes);
-    a.tab_bytes = tab_bytes > LDS_BYTES ? 0u : (uint32_t)tab_bytes;
-
-    // Launch plan.  Chain state in LDS needs at least one full wave per SIMD
-    // (256 lanes per CU) to be worth it; otherwise the state goes to global
-    // memory and more waves hide its latency.  Tables go to LDS when they fit
-    // next to whatever else the workgroup keeps there.
-    int block = 256;
-    bool lds_state = false, lds_tables = false;
-    size_t wg_per_cu = 1;
-    auto fits = [&](int L, bool sl, bool tl) {
-        if (tl && !a.tab_bytes) return false;
-        return mcpd::sampler_lds_bytes(a, L, sl, tl) <= LDS_BYTES;
-    };
-    if (opts.plan > 4) return fail(MCPD_EINVAL, "plan must be 0..4");
-    if (opts.plan == 0) {
-        if (fits(256, true, true)) { lds_state = lds_tables = true; }
-        else if (fits(256, true, false)) { lds_state = true; }
-        else { lds_tables = fits(256, false, true); }
-    } else {
-        lds_state = opts.plan <= 2;
-        lds_tables = opts.plan == 1 || opts.plan == 3;
-        if (!fits(256, lds_state, lds_tables)) return fail(MCPD_EINVAL, "requested plan does not fit in LDS");
+    std::vector<Item> items{Item{I, budget, slots, k, m}};
+    int rc = check_items(items, opts, false);
+    if (rc) return rc;
+    if (!I->single) {
+        I->single = new (std::nothrow) Launch();
+        if (!I->single) return fail(MCPD_ENOMEM, "host allocation failed");
+        I->single->stream = I->stream;
+        I->single->device = I->device;
+        I->single->cus = I->cus;
     }
-    {
-        const size_t per_wg = mcpd::sampler_lds_bytes(a, block, lds_state, lds_tables);
-        const size_t by_lds = per_wg ? LDS_BYTES / per_wg : 8;
-        const size_t by_waves = lds_state ? 2048 / block : 1024 / block;
-        wg_per_cu = std::max<size_t>(1, std::min(by_lds, by_waves));
-        if (opts.wg_per_cu) {
-            if (opts.wg_per_cu > 8 || opts.wg_per_cu > by_lds)
-                return fail(MCPD_EINVAL, "wg_per_cu does not fit");
-            wg_per_cu = opts.wg_per_cu;
-        }
-    }
-    const size_t max_lanes = (size_t)I->cus * wg_per_cu * (size_t)block;
-    const size_t want_lanes = std::min<size_t>(((size_t)slots + block - 1) / block * block, max_lanes);
-    const int grid = (int)(want_lanes / block);
-    const size_t lanes = (size_t)grid * block;
-    // Workspace.  Numerator rows are kept zero between runs by the kernel.
-    int rc;
-    if (I->acc_lanes < lanes || !I->d_acc) {
-        size_t cap = 0;
-        free_ptr(I->d_acc); I->d_acc = nullptr;
-        free_ptr(I->d_lists); I->d_lists = nullptr;
-        I->acc_lanes = 0;
-        if ((rc = ensure(&I->d_acc, cap, lanes * (size_t)n))) return rc;
-        HIP_TRY(hipMemsetAsync(I->d_acc, 0, lanes * (size_t)n * sizeof(int64_t), I->stream));
-        cap = 0;
-        if ((rc = ensure(&I->d_lists, cap, lanes * LIST_CAP))) return rc;
-        I->acc_lanes = lanes;
-    }
-    const size_t words = (size_t)a.words_bits + a.words_cnt;
-    if (!lds_state) {
-        if ((rc = ensure(&I->d_gstate, I->gstate_words, lanes * words))) return rc;
-    }
-    if ((rc = ensure(&I->d_S1, I->bucket_cap, (size_t)nbuckets * n))) return rc;
-    if ((rc = ensure(&I->d_S2, I->bucket2_cap, (size_t)nbuckets * n * 2))) return rc;
-    const size_t small_words = opts.hist_bins + mcpd::ST_COUNT + 2;
-    if ((rc = ensure(&I->d_small, I->small_cap, small_words))) return rc;
-    if (opts.slot_nstar || opts.slot_units) {
-        if (I->slot_cap < slots) {
-            free_ptr(I->d_slot_nstar); free_ptr(I->d_slot_units);
-            I->d_slot_nstar = nullptr; I->d_slot_units = nullptr;
-            size_t c1 = 0, c2 = 0;
-            if ((rc = ensure(&I->d_slot_nstar, c1, slots)) || (rc = ensure(&I->d_slot_units, c2, slots))) {
-                I->slot_cap = 0;
-                return rc;
-            }
-            I->slot_cap = slots;
-        }
-    }
-    if ((rc = ensure(&I->d_lane_stats, I->lane_stats_cap, lanes * mcpd::ST_COUNT))) return rc;
-    a.lane_stats = I->d_lane_stats;
-    a.acc = I->d_acc;
-    a.lists = I->d_lists;
-    a.gstate = lds_state ? nullptr : I->d_gstate;
-    a.S1 = I->d_S1;
-    a.S2 = I->d_S2;
-    a.hist = I->d_small;
-    a.stats = I->d_small + opts.hist_bins;
-    a.ctrl = reinterpret_cast<uint32_t *>(I->d_small + opts.hist_bins + mcpd::ST_COUNT);
-    a.slot_nstar = opts.slot_nstar ? I->d_slot_nstar : nullptr;
-    a.slot_units = opts.slot_units ? I->d_slot_units : nullptr;
-
-    HIP_TRY(hipMemsetAsync(I->d_S1, 0, (size_t)nbuckets * n * sizeof(int64_t), I->stream));
-    HIP_TRY(hipMemsetAsync(I->d_S2, 0, (size_t)nbuckets * n * 2 * sizeof(uint64_t), I->stream));
-    HIP_TRY(hipMemsetAsync(I->d_small, 0, small_words * sizeof(uint64_t), I->stream));
-
-    HIP_TRY(hipEventRecord(I->ev0, I->stream));
-    int e = mcpd::launch_sampler(a, grid, block, lds_state, lds_tables, I->stream);
-    if (e != hipSuccess) return hip_fail((hipError_t)e, "sampler launch");
-    HIP_TRY(hipEventRecord(I->ev1, I->stream));
-
-    std::vector<int64_t> S1((size_t)nbuckets * n);
-    std::vector<uint64_t> S2((size_t)nbuckets * n * 2);
-    std::vector<uint64_t> small(small_words);
-    HIP_TRY(hipMemcpyAsync(S1.data(), I->d_S1, S1.size() * sizeof(int64_t), hipMemcpyDeviceToHost, I->stream));
-    HIP_TRY(hipMemcpyAsync(S2.data(), I->d_S2, S2.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, I->stream));
-    HIP_TRY(hipMemcpyAsync(small.data(), I->d_small, small_words * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                           I->stream));
-    if (opts.slot_nstar)
-        HIP_TRY(hipMemcpyAsync(opts.slot_nstar, I->d_slot_nstar, (size_t)slots * 4, hipMemcpyDeviceToHost, I->stream));
-    if (opts.slot_units)
-        HIP_TRY(hipMemcpyAsync(opts.slot_units, I->d_slot_units, (size_t)slots * 8, hipMemcpyDeviceToHost, I->stream));
-    HIP_TRY(hipStreamSynchronize(I->stream));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, I->ev0, I->ev1));
-
-    const uint32_t *ctrl = reinterpret_cast<const uint32_t *>(small.data() + opts.hist_bins + mcpd::ST_COUNT);
-    if (ctrl[1] & mcpd::ERR_BUCKETS) return fail(MCPD_EINVAL, "internal: N* above bucket count");
-    const uint64_t *st = small.data() + opts.hist_bins;
-
-    // marginal_j = (1/(P W)) sum_n S1[n][j] / n ;  SE from the sums of squares.
-    const long double PW = (long double)slots * (long double)a.W;
-    const long double W = (long double)a.W;
-    for (int32_t j = 0; j < n; ++j) {
-        long double sa = 0.0L, sq = 0.0L;
-        for (uint32_t r = 0; r < nbuckets; ++r) {
-            const size_t idx = (size_t)r * n + j;
-            const long double nn = (long double)(r + 1);
-            sa += (long double)S1[idx] / nn;
-            const long double v2 = (long double)S2[2 * idx + 1] * 18446744073709551616.0L + (long double)S2[2 * idx];
-            sq += v2 / (nn * nn);
-        }
-        marginals[j] = (double)(sa / PW);
-        if (slots > 1) {
-            const long double sumA = sa / W, sumA2 = sq / (W * W);
-            long double var = (sumA2 - sumA * sumA / (long double)slots) / (long double)(slots - 1);
-            if (var < 0) var = 0;
-            stderr_out[j] = (double)std::sqrt(var / (long double)slots);
-        } else {
-            stderr_out[j] = NAN;
-        }
-    }
-    if (hist) std::memcpy(hist, small.data(), sizeof(uint64_t) * opts.hist_bins);
-    if (opts.bucket_sum || opts.bucket_sumsq) {
-        if (st[mcpd::ST_NSTAR_MAX] > opts.bucket_rows) return fail(MCPD_EINVAL, "bucket_rows below N*");
-        const size_t rows = std::min<size_t>(opts.bucket_rows, nbuckets);
-        if (opts.bucket_sum) {
-            std::memset(opts.bucket_sum, 0, sizeof(int64_t) * (size_t)opts.bucket_rows * n);
-            std::memcpy(opts.bucket_sum, S1.data(), sizeof(int64_t) * rows * n);
-        }
-        if (opts.bucket_sumsq) {
-            std::memset(opts.bucket_sumsq, 0, sizeof(uint64_t) * 2 * (size_t)opts.bucket_rows * n);
-            std::memcpy(opts.bucket_sumsq, S2.data(), sizeof(uint64_t) * 2 * rows * n);
-        }
-    }
-    if (stats) {
-        stats->progress_units = st[mcpd::ST_PROGRESS];
-        stats->retained_units = st[mcpd::ST_RETAINED_UNITS];
-        stats->single_site_updates = st[mcpd::ST_SINGLE_SITE];
-        stats->reps_started = st[mcpd::ST_REPS_STARTED];
-        stats->reps_retained = st[mcpd::ST_REPS_RETAINED];
-        stats->reps_aborted = st[mcpd::ST_REPS_ABORTED];
-        stats->cap_hits = st[mcpd::ST_CAP_HITS];
-        stats->zero_completion_slots = st[mcpd::ST_ZERO_COMPLETION];
-        stats->tau_sum = st[mcpd::ST_TAU_SUM];
-        stats->tau_max = st[mcpd::ST_TAU_MAX];
-        stats->nstar_max = st[mcpd::ST_NSTAR_MAX];
-        stats->rollback_units = st[mcpd::ST_ROLLBACK_UNITS];
-        stats->kernel_ms = ms;
-        stats->lanes = (uint64_t)lanes;
-        stats->lds_state = (lds_state ? 1u : 0u) | (lds_tables ? 2u : 0u);
-    }
-    if (opts.strict_cap && st[mcpd::ST_CAP_HITS]) return fail(MCPD_ECAP, "a retained pair hit the meeting cap");
-    return MCPD_OK;
+    Launch &L = *I->single;
+    L.items = items;
+    L.opts = opts;
+    L.batch_ids = false;
+    L.slot_records = opts.slot_nstar || opts.slot_units;
+    L.fmt = pick_format(I->m > 127, I->dmax);
+    Config c = default_config(L);
+    if ((rc = plan(L, c))) return rc;
+    if ((rc = execute(L, seed, false))) return rc;
+    if (L.slot_records && (rc = copy_slot_records(L, 0, opts.slot_nstar, opts.slot_units))) return rc;
+    if ((opts.bucket_sum || opts.bucket_sumsq) &&
+        (rc = copy_buckets(L, 0, opts.bucket_rows, opts.bucket_sum, opts.bucket_sumsq)))
+        return rc;
+    return finish_item(L, 0, marginals, stderr_out, hist, stats);
 }
 
 void mcpd_destroy(mcpd_instance *I)
 {
     if (!I) return;
     (void)hipStreamSynchronize(I->stream);
-    release(I);
+    mcpd::host::release(I);
     delete I;
+}
+
+int mcpd_batch_create(mcpd_instance *const *insts, int32_t count, const uint64_t *budget, const uint32_t *slots,
+                      const uint32_t *k, const uint32_t *m, const mcpd_run_opts *opts_in, void *hip_stream,
+                      mcpd_batch **out)
+{
+    using namespace mcpd::host;
+    if (!out) return fail(MCPD_EINVAL, "out is null");
+    *out = nullptr;
+    if (count <= 0 || !insts || !budget || !slots || !k || !m) return fail(MCPD_EINVAL, "empty or null batch");
+    mcpd_run_opts opts;
+    if (opts_in) opts = *opts_in; else mcpd_run_opts_init(&opts);
+    if (opts.slot_nstar || opts.slot_units || opts.bucket_sum || opts.bucket_sumsq)
+        return fail(MCPD_EINVAL, "batch runs take no per-run output pointers in opts");
+    std::vector<Item> items((size_t)count);
+    bool wide = false;
+    int need = 1;
+    for (int32_t i = 0; i < count; ++i) {
+        items[i] = Item{insts[i], budget[i], slots[i], k[i], m[i]};
+        if (!insts[i]) return fail(MCPD_EINVAL, "null instance in batch");
+        wide = wide || insts[i]->m > 127;
+        need = std::max(need, insts[i]->dmax);
+    }
+    int rc = check_items(items, opts, true);
+    if (rc) return rc;
+    std::unique_ptr<mcpd_batch> b(new (std::nothrow) mcpd_batch());
+    if (!b) return fail(MCPD_ENOMEM, "host allocation failed");
+    b->L.reset(new (std::nothrow) Launch());
+    if (!b->L) return fail(MCPD_ENOMEM, "host allocation failed");
+    Launch &L = *b->L;
+    L.items = std::move(items);
+    L.opts = opts;
+    L.batch_ids = true;
+    L.slot_records = opts.keep_slot_records != 0;
+    L.fmt = pick_format(wide, need);
+    HIP_TRY(hipGetDevice(&L.device));
+    HIP_TRY(hipDeviceGetAttribute(&L.cus, hipDeviceAttributeMultiprocessorCount, L.device));
+    if (hip_stream) {
+        L.stream = reinterpret_cast<hipStream_t>(hip_stream);
+    } else {
+        // graphs cannot be captured on the legacy default stream
+        HIP_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+        L.own_stream = true;
+    }
+    if ((rc = plan(L, default_config(L)))) return rc;
+    *out = b.release();
+    return MCPD_OK;
+}
+
+int mcpd_batch_run(mcpd_batch *b, uint64_t seed, double *const *marginals, double *const *stderr_out,
+                   uint64_t *const *hist, mcpd_run_stats *stats)
+{
+    using namespace mcpd::host;
+    if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
+    Launch &L = *b->L;
+    int rc = execute(L, seed, L.opts.use_graph != 0);
+    if (rc) return rc;
+    int first = MCPD_OK;
+    for (size_t i = 0; i < L.items.size(); ++i) {
+        rc = finish_item(L, i, marginals ? marginals[i] : nullptr, stderr_out ? stderr_out[i] : nullptr,
+                         hist ? hist[i] : nullptr, stats ? stats + i : nullptr);
+        if (rc && !first) first = rc;
+    }
+    return first;
+}
+
+int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint32_t cap, uint32_t *count)
+{
+    using namespace mcpd::host;
+    if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
+    Launch &L = *b->L;
+    // Candidates: workgroups per CU (registers allow three waves of the
+    // sampler per SIMD) x slots per lane per ticket.
+    std::vector<Config> cands;
+    const uint32_t wgs[] = {1, 2, 3};
+    const uint32_t spls[] = {1, 2, 4};
+    for (uint32_t w : wgs) {
+        if (L.opts.wg_per_cu && w != L.opts.wg_per_cu) continue;
+        for (uint32_t s : spls) {
+            if (L.opts.ticket_slots && s != L.opts.ticket_slots) continue;
+            Config c;
+            c.wg_per_cu = w;
+            c.spl = s;
+            cands.push_back(c);
+        }
+    }
+    Config best = L.cfg;
+    double best_ms = INFINITY;
+    uint32_t done = 0;
+    for (const Config &c : cands) {
+        int rc = plan(L, c);
+        if (rc == MCPD_ENOMEM) continue;   // too much numerator workspace at this width
+        if (rc) return rc;
+        if ((rc = execute(L, seed, false))) return rc;
+        const double ms = L.last_ms;
+        if (entries && done < cap) entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, ms};
+        ++done;
+        if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    if (count) *count = done;
+    if (!done) return fail(MCPD_ENOMEM, "no tuning candidate fits in device memory");
+    return plan(L, best);
+}
+
+int mcpd_batch_config(const mcpd_batch *b, uint32_t *wg_per_cu, uint32_t *ticket_slots, uint32_t *lanes,
+                      uint32_t *placement)
+{
+    using namespace mcpd::host;
+    if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
+    const Launch &L = *b->L;
+    if (wg_per_cu) *wg_per_cu = L.cfg.wg_per_cu;
+    if (ticket_slots) *ticket_slots = L.cfg.spl;
+    if (lanes) *lanes = (uint32_t)L.grid * mcpd::WG_LANES;
+    if (placement)
+        for (size_t i = 0; i < L.desc.size(); ++i) placement[i] = L.desc[i].place;
+    return MCPD_OK;
+}
+
+int mcpd_batch_buckets(const mcpd_batch *b, int32_t index, uint32_t rows, int64_t *sum, uint64_t *sumsq)
+{
+    using namespace mcpd::host;
+    if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
+    if (index < 0 || (size_t)index >= b->L->items.size()) return fail(MCPD_EINVAL, "index out of range");
+    return copy_buckets(*b->L, (size_t)index, rows, sum, sumsq);
+}
+
+int mcpd_batch_slot_records(mcpd_batch *b, int32_t index, uint32_t *nstar, uint64_t *units)
+{
+    using namespace mcpd::host;
+    if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
+    if (index < 0 || (size_t)index >= b->L->items.size()) return fail(MCPD_EINVAL, "index out of range");
+    return copy_slot_records(*b->L, (size_t)index, nstar, units);
+}
+
+void mcpd_batch_destroy(mcpd_batch *b)
+{
+    delete b;
+}
+
+int mcpd_run_batch(mcpd_instance *const *insts, int32_t count, const uint64_t *budget, const uint32_t *slots,
+                   const uint32_t *k, const uint32_t *m, uint64_t seed, const mcpd_run_opts *opts,
+                   double *const *marginals, double *const *stderr_out, uint64_t *const *hist,
+                   mcpd_run_stats *stats)
+{
+    mcpd_batch *b = nullptr;
+    int rc = mcpd_batch_create(insts, count, budget, slots, k, m, opts, nullptr, &b);
+    if (rc) return rc;
+    rc = mcpd_batch_run(b, seed, marginals, stderr_out, hist, stats);
+    mcpd_batch_destroy(b);
+    return rc;
 }
 
 }  // extern "C"

@@ -4,9 +4,15 @@
 // One lane owns one logical slot at a time (Algorithm 4: "the GPU scheduler
 // maps a logical slot p to one persistent thread") and runs its i.i.d.
 // coupled replications (Algorithm 3) one after the other.  Slots are handed
-// out dynamically from a global counter; the result does not depend on which
-// lane runs which slot because every random number is keyed by
+// out dynamically from a per-instance counter; the result does not depend on
+// which lane runs which slot because every random number is keyed by
 // (instance, slot, replication, draw).
+//
+// One launch serves a batch of instances of any sizes.  A workgroup takes a
+// ticket from a global queue, which names the instance it joins; it places
+// that instance's tables (and chain state, if it fits) in LDS, its lanes take
+// the instance's slots until none is left, and the workgroup takes the next
+// ticket.  The host orders the tickets (longest slots first) and sizes them.
 //
 // Per-lane chain state (both chains X and Y):
 //   bit words   : 16 clones per dword, clone i at bits 2(i mod 16) (x) and
@@ -43,9 +49,13 @@
 // completion-time-corrected aggregate exact and order-independent.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mcpd_device.h"
 
 namespace mcpd {
+
+#if defined(MCPD_FMT)
 namespace {
 
 constexpr uint32_t MODE_NEED_SLOT = 0;
@@ -54,7 +64,12 @@ constexpr uint32_t MODE_RUN = 2;
 constexpr uint32_t MODE_DONE = 3;
 constexpr uint32_t NO_TAG = 0xFFFFFFFFu;
 constexpr int CACHE = 8;
-constexpr uint32_t WG = 256;   // lanes per workgroup (state stride), fixed at launch
+constexpr uint32_t WG = WG_LANES;   // lanes per workgroup (state stride), fixed at launch
+
+// The instance descriptors are read-only for the whole launch: reading them
+// through the constant address space lets the compiler use scalar loads and
+// reload them instead of keeping every field live.
+using DescPtr = const __attribute__((address_space(4))) InstDesc *;
 
 // Philox4x32-10 (Salmon et al., SC'11).  The key is wave-uniform, so its
 // schedule stays on the scalar unit.
@@ -133,7 +148,9 @@ struct Row {
 
 template <bool SL, bool TL, int F>
 struct Sampler {
-    const RunArgs &a;
+    const LaunchArgs &a;
+    DescPtr D;
+    uint32_t k0, k1;        // the key of the random numbers
     uint32_t *st;           // this workgroup's state base (LDS or global)
     const uint64_t *thr;    // tables (LDS copies or global)
     const uint32_t *alias;
@@ -145,7 +162,7 @@ struct Sampler {
     uint32_t *hist_lds;
 
     __device__ __forceinline__ uint32_t &bits(uint32_t w) const { return st[w * WG + lane]; }
-    __device__ __forceinline__ uint32_t &cnt(uint32_t q) const { return st[(a.words_bits + q) * WG + lane]; }
+    __device__ __forceinline__ uint32_t &cnt(uint32_t q) const { return st[(D->words_bits + q) * WG + lane]; }
 
     // Statistic slots and spill rows belong to one lane: workgroup-scope
     // atomics keep them in the L2 of the lane's XCD instead of memory.
@@ -158,9 +175,9 @@ struct Sampler {
         __hip_atomic_fetch_max(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
-    __device__ void reset_state() const
+    __device__ __forceinline__ void reset_state() const
     {
-        const uint32_t nw = a.words_bits + a.words_cnt;
+        const uint32_t nw = D->words_bits + D->words_cnt;
         for (uint32_t w = 0; w < nw; ++w) st[w * WG + lane] = 0u;
     }
 
@@ -168,10 +185,10 @@ struct Sampler {
     // the window, the cap, the end of a replay, or the abort point.
     __device__ __forceinline__ void set_limit(Lane &s) const
     {
-        uint32_t lim = a.ell < a.capmax ? a.ell : a.capmax;
+        uint32_t lim = D->ell < D->capmax ? D->ell : D->capmax;
         if (s.sgn < 0 && s.target < lim) lim = s.target;
         if (s.r >= 2u) {
-            const uint64_t ab = a.B - s.S + 1u;
+            const uint64_t ab = D->B - s.S + 1u;
             if (ab < (uint64_t)lim) lim = (uint32_t)ab;
         }
         s.lim = lim;
@@ -216,10 +233,10 @@ struct Sampler {
     }
 
     // Low 53-b bits of U of draw t (block (t, r, p, g | 2^24)).
-    __device__ uint64_t low_bits(const Lane &s, uint32_t t) const
+    __device__ __forceinline__ uint64_t low_bits(const Lane &s, uint32_t t) const
     {
         uint32_t o[4];
-        philox10(t, s.r, s.p, a.g | (1u << 24), (uint32_t)a.seed, (uint32_t)(a.seed >> 32), o);
+        philox10(t, s.r, s.p, D->g | (1u << 24), k0, k1, o);
         const uint64_t v = ((uint64_t)o[0] << 32) | (uint64_t)o[1];
         return v >> (11u + a.ubits);
     }
@@ -241,7 +258,7 @@ struct Sampler {
     // coin from the low bits (one LDS read, no search).
     __device__ __forceinline__ uint32_t site(uint32_t sw) const
     {
-        const uint32_t cb = 32u - a.T.abits;
+        const uint32_t cb = 32u - D->abits;
         const uint32_t col = sw >> cb;
         const uint32_t aw = alias[col];
         const uint32_t kmask = (1u << cb) - 1u;
@@ -324,12 +341,12 @@ struct Sampler {
             // estimator events at time te = t + 1
             uint64_t val = 0;
             const uint32_t te = t + 1u;
-            if (dx != 0 && te <= a.ell) {
-                const uint32_t from = te > a.k ? te : a.k;
-                val += (uint64_t)(int64_t)dx * (uint64_t)(a.ell - from + 1u);
+            if (dx != 0 && te <= D->ell) {
+                const uint32_t from = te > D->k ? te : D->k;
+                val += (uint64_t)(int64_t)dx * (uint64_t)(D->ell - from + 1u);
             }
-            if (updY && t >= a.k + 1u && dx != dy)
-                val -= (uint64_t)(int64_t)(dx - dy) * gsum(t, a.k, a.ell, a.W);
+            if (updY && t >= D->k + 1u && dx != dy)
+                val -= (uint64_t)(int64_t)(dx - dy) * gsum(t, D->k, D->ell, D->W);
             if (val != 0) event(s, I, s.sgn > 0 ? val : (uint64_t)0 - val);
         }
         if (s.tau == 0u && s.mu == 0) s.tau = t + 1u;
@@ -337,12 +354,12 @@ struct Sampler {
     }
 
     // Boundary term G(C) Delta_j(C) of a pair stopped by the cap.
-    __device__ void truncation(Lane &s) const
+    __device__ __forceinline__ void truncation(Lane &s) const
     {
         const uint32_t C = s.t;
-        if (C < a.k + 1u) return;
-        const uint64_t G = gsum(C, a.k, a.ell, a.W);
-        for (uint32_t w = 0; w < a.words_bits; ++w) {
+        if (C < D->k + 1u) return;
+        const uint64_t G = gsum(C, D->k, D->ell, D->W);
+        for (uint32_t w = 0; w < D->words_bits; ++w) {
             const uint32_t word = bits(w);
             uint32_t mis = (word ^ (word >> 1)) & 0x55555555u;
             while (mis) {
@@ -355,26 +372,26 @@ struct Sampler {
         }
     }
 
-    __device__ void emit(uint32_t nstar, uint32_t j, int64_t v) const
+    __device__ __forceinline__ void emit(uint32_t nstar, uint32_t j, int64_t v) const
     {
-        if (nstar > a.nbuckets) {
+        if (nstar > D->nbuckets) {
             atomicOr(&a.ctrl[1], (uint32_t)ERR_BUCKETS);
             return;
         }
-        const size_t idx = (size_t)(nstar - 1u) * (size_t)a.T.n + j;
-        atomicAdd(reinterpret_cast<unsigned long long *>(a.S1 + idx), (unsigned long long)v);
+        const size_t idx = (size_t)(nstar - 1u) * (size_t)D->n + j;
+        atomicAdd(reinterpret_cast<unsigned long long *>(D->S1 + idx), (unsigned long long)v);
         const uint64_t u = v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
         const uint64_t lo = u * u;
         const uint64_t hi = __umul64hi(u, u);
         const unsigned long long old =
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.S2 + 2 * idx), (unsigned long long)lo);
+            atomicAdd(reinterpret_cast<unsigned long long *>(D->S2 + 2 * idx), (unsigned long long)lo);
         const uint64_t carry = ((uint64_t)old + lo < (uint64_t)old) ? 1u : 0u;
         if (hi + carry)
-            atomicAdd(reinterpret_cast<unsigned long long *>(a.S2 + 2 * idx + 1),
+            atomicAdd(reinterpret_cast<unsigned long long *>(D->S2 + 2 * idx + 1),
                       (unsigned long long)(hi + carry));
     }
 
-    __device__ void flush_slot(Lane &s) const
+    __device__ __forceinline__ void flush_slot(Lane &s) const
     {
         const uint32_t nstar = s.nret;
 #pragma unroll
@@ -392,20 +409,21 @@ struct Sampler {
                     if (v != 0) emit(nstar, j, v);
                 }
             } else {
-                for (uint32_t j = 0; j < (uint32_t)a.T.n; ++j) {
+                stat_add(ST_LIST_OVERFLOWS, 1);
+                for (uint32_t j = 0; j < (uint32_t)D->n; ++j) {
                     const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
                                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     if (v != 0) emit(nstar, j, v);
                 }
             }
         }
-        if (a.slot_nstar) a.slot_nstar[s.p] = nstar;
-        if (a.slot_units) a.slot_units[s.p] = s.S;
+        if (D->slot_nstar) D->slot_nstar[s.p] = nstar;
+        if (D->slot_units) D->slot_units[s.p] = s.S;
         stat_max(ST_NSTAR_MAX, nstar);
         s.mode = MODE_NEED_SLOT;
     }
 
-    __device__ void begin_rollback(Lane &s, uint32_t draws) const
+    __device__ __forceinline__ void begin_rollback(Lane &s, uint32_t draws) const
     {
         stat_add(ST_REPS_ABORTED, 1);
         stat_add(ST_ROLLBACK_UNITS, draws);
@@ -417,11 +435,11 @@ struct Sampler {
 
     // Bookkeeping once the draw count reaches the lane's limit: completion,
     // retention, abort, end of replay.
-    __device__ void after_step(Lane &s) const
+    __device__ __forceinline__ void after_step(Lane &s) const
     {
         const uint32_t d = s.t;
-        const bool capped = (s.tau == 0u) && (d >= a.capmax);
-        const bool ended = capped || (s.tau != 0u && d >= a.ell);
+        const bool capped = (s.tau == 0u) && (d >= D->capmax);
+        const bool ended = capped || (s.tau != 0u && d >= D->ell);
         if (s.sgn < 0) {
             if (d == s.target) {
                 if (capped) truncation(s);
@@ -432,7 +450,7 @@ struct Sampler {
         if (ended) {
             if (capped) truncation(s);
             const uint64_t C = d;
-            const bool retained = (s.r == 1u) || (s.S + C <= a.B);
+            const bool retained = (s.r == 1u) || (s.S + C <= D->B);
             if (!retained) { begin_rollback(s, d); return; }
             s.S += C;
             s.nret += 1u;
@@ -447,16 +465,16 @@ struct Sampler {
                 stat_add(ST_SINGLE_SITE, 1 + 2 * (mt - 1) + (C - mt));
                 stat_add(ST_TAU_SUM, s.tau);
                 stat_max(ST_TAU_MAX, s.tau);
-                uint32_t bin = s.tau / a.hist_width;
+                uint32_t bin = s.tau / D->hist_width;
                 if (bin >= a.hist_bins) bin = a.hist_bins - 1u;
                 atomicAdd(hist_lds + bin, 1u);
             }
-            if (s.r == 1u && C > a.B) stat_add(ST_ZERO_COMPLETION, 1);
-            if (!a.refill || s.S >= a.B || s.S + a.cmin > a.B) flush_slot(s);
+            if (s.r == 1u && C > D->B) stat_add(ST_ZERO_COMPLETION, 1);
+            if (!a.refill || s.S >= D->B || s.S + D->cmin > D->B) flush_slot(s);
             else s.mode = MODE_NEED_REP;
             return;
         }
-        if (s.r >= 2u && (uint64_t)d > a.B - s.S) begin_rollback(s, d);
+        if (s.r >= 2u && (uint64_t)d > D->B - s.S) begin_rollback(s, d);
     }
 };
 
@@ -467,21 +485,21 @@ __device__ __forceinline__ void copy_to_lds(uint32_t *dst, const void *src, uint
     for (uint32_t i = threadIdx.x; i < n32; i += blockDim.x) dst[i] = s[i];
 }
 
+// One workgroup's share of one instance: place the tables (and state) in
+// LDS, let every lane take slots until the instance has none left, then add
+// the lanes' statistics and the histogram to the instance's totals.
 template <bool SL, bool TL, int F>
-__global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
+__device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_t *smem, uint32_t k0, uint32_t k1)
 {
-    extern __shared__ uint32_t smem[];
     constexpr uint32_t L = WG;
     const uint32_t lane = threadIdx.x;
-    const uint32_t words = a.words_bits + a.words_cnt;
-    uint32_t *after_state = SL ? smem + (size_t)words * L : smem;
-    uint32_t *hist_lds = after_state;
-    uint32_t *tab = after_state + ((a.hist_bins + 3u) & ~3u);   // keeps 16-byte alignment
+    uint32_t *hist_lds = smem + D->lds_hist;
+    uint32_t *tab = smem + D->lds_tab;
     for (uint32_t b = lane; b < a.hist_bins; b += L) hist_lds[b] = 0u;
     if (TL) {
-        copy_to_lds(tab + a.tab_off_thr / 4, a.T.thr, a.T.thr_len * 2u);
-        copy_to_lds(tab + a.tab_off_alias / 4, a.T.alias, 1u << a.T.abits);
-        copy_to_lds(tab + a.tab_off_rows / 4, a.T.rows, (uint32_t)a.T.n * a.T.row_bytes / 4u);
+        copy_to_lds(tab + D->tab_off_thr / 4, D->thr, D->thr_len * 2u);
+        copy_to_lds(tab + D->tab_off_alias / 4, D->alias, 1u << D->abits);
+        copy_to_lds(tab + D->tab_off_rows / 4, D->rows, (uint32_t)D->n * D->row_bytes / 4u);
     }
     const size_t gl = (size_t)blockIdx.x * L + lane;
     uint64_t *ls = a.lane_stats + gl * ST_COUNT;
@@ -490,12 +508,15 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
     __syncthreads();
 
     Sampler<SL, TL, F> S{a,
-                         SL ? smem : a.gstate + (size_t)blockIdx.x * words * WG,
-                         TL ? reinterpret_cast<const uint64_t *>(tab + a.tab_off_thr / 4) : a.T.thr,
-                         TL ? tab + a.tab_off_alias / 4 : a.T.alias,
-                         TL ? tab + a.tab_off_rows / 4 : a.T.rows,
+                         D,
+                         k0,
+                         k1,
+                         SL ? smem : a.gstate + (size_t)blockIdx.x * a.gwords * WG,
+                         TL ? reinterpret_cast<const uint64_t *>(tab + D->tab_off_thr / 4) : D->thr,
+                         TL ? tab + D->tab_off_alias / 4 : D->alias,
+                         TL ? tab + D->tab_off_rows / 4 : D->rows,
                          lane,
-                         a.acc + gl * (size_t)a.T.n,
+                         a.acc + gl * (size_t)a.acc_stride,
                          a.lists + gl * (size_t)a.list_cap,
                          ls,
                          hist_lds};
@@ -509,7 +530,9 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
     s.f0 = s.f1 = NO_TAG;
 #pragma unroll
     for (int e = 0; e < CACHE; ++e) { s.ctag[e] = NO_TAG; s.cval[e] = 0; }
-    const uint32_t k0 = (uint32_t)a.seed, k1 = (uint32_t)(a.seed >> 32);
+    const uint32_t P = D->P;
+    const uint32_t g = D->g;
+    uint32_t *next_slot = D->next_slot;
 
     // Pipeline registers: the random block of the current pair of draws
     // (t, t+1) and the site and row of draw t, fetched one draw ahead.
@@ -522,8 +545,8 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
     for (;;) {
         if (s.mode != MODE_RUN) {
             if (s.mode == MODE_NEED_SLOT) {
-                const uint32_t p = atomicAdd(&a.ctrl[0], 1u);
-                if (p >= a.P) {
+                const uint32_t p = atomicAdd(next_slot, 1u);
+                if (p >= P) {
                     s.mode = MODE_DONE;
                 } else {
                     s.p = p;
@@ -546,7 +569,7 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
                 s.tau = 0;
                 s.mu = 0;
                 S.set_limit(s);
-                philox10(0u, s.r, s.p, a.g, k0, k1, w);
+                philox10(0u, s.r, s.p, g, k0, k1, w);
                 curI = S.site(w[0]);
                 cur.load(S.rows, curI);
                 s.mode = MODE_RUN;
@@ -558,7 +581,7 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
             // random block and draw t+1's site and row while they are in flight
             const typename Sampler<SL, TL, F>::Loads l0 = S.issue(curI, cur);
             uint32_t nx[4];
-            philox10((s.t >> 1) + 1u, s.r, s.p, a.g, k0, k1, nx);
+            philox10((s.t >> 1) + 1u, s.r, s.p, g, k0, k1, nx);
             const uint32_t I1 = S.site(w[2]);
             Row<F> r1;
             r1.load(S.rows, I1);
@@ -582,6 +605,7 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
 
     // Statistics: each lane reads back its own slots, wave reduction, then
     // one atomic per wave.
+    uint64_t *stats = D->stats;
 #pragma unroll
     for (int i = 0; i < ST_COUNT; ++i) {
         uint64_t v = __hip_atomic_load(ls + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -590,63 +614,109 @@ __global__ void __launch_bounds__(256) sampler_kernel(RunArgs a)
             const uint64_t o = __shfl_xor(v, off);
             v = is_max ? (o > v ? o : v) : v + o;
         }
-        if ((lane & 63u) == 0u) {
-            if (is_max) atomicMax(reinterpret_cast<unsigned long long *>(a.stats + i), (unsigned long long)v);
-            else atomicAdd(reinterpret_cast<unsigned long long *>(a.stats + i), (unsigned long long)v);
+        if ((lane & 63u) == 0u && v != 0) {
+            if (is_max) atomicMax(reinterpret_cast<unsigned long long *>(stats + i), (unsigned long long)v);
+            else atomicAdd(reinterpret_cast<unsigned long long *>(stats + i), (unsigned long long)v);
         }
     }
     __syncthreads();
+    uint64_t *hist = D->hist;
     for (uint32_t b = lane; b < a.hist_bins; b += L)
-        if (hist_lds[b]) atomicAdd(reinterpret_cast<unsigned long long *>(a.hist + b), (unsigned long long)hist_lds[b]);
+        if (hist_lds[b]) atomicAdd(reinterpret_cast<unsigned long long *>(hist + b), (unsigned long long)hist_lds[b]);
+    __syncthreads();
 }
 
-template <bool SL, bool TL, int F>
-int launch_one(const RunArgs &a, int grid, int block, size_t lds, hipStream_t st)
+// Persistent kernel over a batch: a workgroup takes tickets until the queue
+// is empty.  Every workgroup leaves when the ticket counter passes the end,
+// and every lane leaves an instance when its slot counter passes P, so the
+// grid always drains.
+template <int F>
+__global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
 {
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(sampler_kernel<SL, TL, F>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return (int)e;
-    }
-    hipLaunchKernelGGL((sampler_kernel<SL, TL, F>), dim3(grid), dim3(block), lds, st, a);
-    return (int)hipGetLastError();
-}
-
-template <bool SL, bool TL>
-int launch_fmt(const RunArgs &a, int grid, int block, size_t lds, hipStream_t st)
-{
-    switch (a.T.fmt) {
-    case FMT_U8_4: return launch_one<SL, TL, FMT_U8_4>(a, grid, block, lds, st);
-    case FMT_U8_5: return launch_one<SL, TL, FMT_U8_5>(a, grid, block, lds, st);
-    case FMT_U8_8: return launch_one<SL, TL, FMT_U8_8>(a, grid, block, lds, st);
-    case FMT_U8_12: return launch_one<SL, TL, FMT_U8_12>(a, grid, block, lds, st);
-    case FMT_U16_4: return launch_one<SL, TL, FMT_U16_4>(a, grid, block, lds, st);
-    case FMT_U16_8: return launch_one<SL, TL, FMT_U16_8>(a, grid, block, lds, st);
-    case FMT_U16_12: return launch_one<SL, TL, FMT_U16_12>(a, grid, block, lds, st);
-    default: return (int)hipErrorInvalidValue;
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t sh_item, sh_skip;
+    const uint64_t seed = *(const __attribute__((address_space(4))) uint64_t *)a.seed;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    DescPtr descs = (DescPtr)a.inst;
+    const __attribute__((address_space(4))) uint32_t *tickets =
+        (const __attribute__((address_space(4))) uint32_t *)a.tickets;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t it = atomicAdd(&a.ctrl[0], 1u);
+            uint32_t skip = 1;
+            if (it < a.nticket) {
+                const InstDesc *d = a.inst + a.tickets[it];
+                skip = __hip_atomic_load(d->next_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= d->P;
+            }
+            sh_item = it;
+            sh_skip = skip;
+        }
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(sh_item);
+        const uint32_t skip = __builtin_amdgcn_readfirstlane(sh_skip);
+        __syncthreads();
+        if (item >= a.nticket) break;
+        if (skip) continue;
+        DescPtr D = descs + tickets[item];
+        switch (D->place) {
+        case PLACE_STATE_LDS | PLACE_TABLES_LDS: run_item<true, true, F>(a, D, smem, k0, k1); break;
+        case PLACE_STATE_LDS: run_item<true, false, F>(a, D, smem, k0, k1); break;
+        case PLACE_TABLES_LDS: run_item<false, true, F>(a, D, smem, k0, k1); break;
+        default: run_item<false, false, F>(a, D, smem, k0, k1); break;
+        }
     }
 }
 
 }  // namespace
 
-size_t sampler_lds_bytes(const RunArgs &a, int block, bool lds_state, bool lds_tables)
+// Launch of the sampler for row format F.  The build compiles this file once
+// per format with MCPD_FMT set (the instantiations take most of the compile
+// time) and once without it for the dispatcher and the fill kernel.
+template <int F>
+int launch_sampler_fmt(const LaunchArgs &a, int grid, size_t lds, void *stream)
 {
-    const size_t words = (size_t)a.words_bits + a.words_cnt;
-    return (lds_state ? words * (size_t)block * 4u : 0u) + (size_t)((a.hist_bins + 3u) & ~3u) * 4u +
-           (lds_tables ? (size_t)a.tab_bytes : 0u);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(sampler_kernel<F>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return (int)e;
+    }
+    hipLaunchKernelGGL((sampler_kernel<F>), dim3(grid), dim3(WG), lds, st, a);
+    return (int)hipGetLastError();
 }
 
-int launch_sampler(const RunArgs &a, int grid, int block, bool lds_state, bool lds_tables, void *stream)
+template int launch_sampler_fmt<MCPD_FMT>(const LaunchArgs &, int, size_t, void *);
+
+#else
+
+__global__ void fill_zero_kernel(uint64_t *p, size_t n)
 {
-    if (block != (int)WG) return (int)hipErrorInvalidValue;   // the state stride is compiled in
-    const size_t lds = sampler_lds_bytes(a, block, lds_state, lds_tables);
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (lds_state) {
-        return lds_tables ? launch_fmt<true, true>(a, grid, block, lds, st)
-                          : launch_fmt<true, false>(a, grid, block, lds, st);
-    }
-    return lds_tables ? launch_fmt<false, true>(a, grid, block, lds, st)
-                      : launch_fmt<false, false>(a, grid, block, lds, st);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
+
+int launch_sampler(const LaunchArgs &a, int fmt, int grid, size_t lds, void *stream)
+{
+    switch (fmt) {
+    case FMT_U8_4: return launch_sampler_fmt<FMT_U8_4>(a, grid, lds, stream);
+    case FMT_U8_5: return launch_sampler_fmt<FMT_U8_5>(a, grid, lds, stream);
+    case FMT_U8_8: return launch_sampler_fmt<FMT_U8_8>(a, grid, lds, stream);
+    case FMT_U8_12: return launch_sampler_fmt<FMT_U8_12>(a, grid, lds, stream);
+    case FMT_U16_4: return launch_sampler_fmt<FMT_U16_4>(a, grid, lds, stream);
+    case FMT_U16_8: return launch_sampler_fmt<FMT_U16_8>(a, grid, lds, stream);
+    case FMT_U16_12: return launch_sampler_fmt<FMT_U16_12>(a, grid, lds, stream);
+    default: return (int)hipErrorInvalidValue;
+    }
+}
+
+int launch_fill_zero(uint64_t *p, size_t n64, void *stream)
+{
+    if (n64 == 0) return (int)hipSuccess;
+    const size_t blocks = std::min<size_t>((n64 + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), p, n64);
+    return (int)hipGetLastError();
+}
+#endif
 
 }  // namespace mcpd

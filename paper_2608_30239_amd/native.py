@@ -41,33 +41,43 @@ class RunOpts(C.Structure):
         ("instance_id", C.c_uint32),
         ("plan", C.c_uint32),
         ("wg_per_cu", C.c_uint32),
+        ("ticket_slots", C.c_uint32),
+        ("use_graph", C.c_uint32),
+        ("keep_slot_records", C.c_uint32),
+        ("bucket_rows", C.c_uint32),
         ("slot_nstar", C.c_void_p),
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),
         ("bucket_sumsq", C.c_void_p),
-        ("bucket_rows", C.c_uint32),
     ]
 
 
 STAT_FIELDS = ("progress_units", "retained_units", "single_site_updates", "reps_started",
                "reps_retained", "reps_aborted", "cap_hits", "zero_completion_slots", "tau_sum",
-               "tau_max", "nstar_max", "rollback_units", "lanes")
+               "tau_max", "nstar_max", "rollback_units", "list_overflows", "lanes")
 
 
 class RunStats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [
-        ("lds_state", C.c_uint32), ("reserved", C.c_uint32), ("kernel_ms", C.c_double)]
+        ("placement", C.c_uint32), ("wg_per_cu", C.c_uint32), ("kernel_ms", C.c_double)]
 
     def as_dict(self):
         d = {f: int(getattr(self, f)) for f in STAT_FIELDS}
-        d["lds_state"] = int(self.lds_state)
+        d["placement"] = int(self.placement)
+        d["wg_per_cu"] = int(self.wg_per_cu)
         d["kernel_ms"] = float(self.kernel_ms)
         return d
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("wg_per_cu", C.c_uint32), ("ticket_slots", C.c_uint32), ("ms", C.c_double)]
+
+
 # Every symbol include/mcpd.h declares.
 EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_create", "mcpd_set_weights",
-           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_destroy", "mcpd_strerror",
+           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_destroy", "mcpd_batch_create",
+           "mcpd_batch_run", "mcpd_batch_tune", "mcpd_batch_config", "mcpd_batch_buckets",
+           "mcpd_batch_slot_records", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_strerror",
            "mcpd_last_error")
 
 _lock = threading.Lock()
@@ -98,6 +108,16 @@ def load(path: Optional[str] = None):
                                         C.POINTER(RunStats)]
         L.mcpd_destroy.argtypes = [vp]
         L.mcpd_destroy.restype = None
+        L.mcpd_batch_create.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(RunOpts), vp, C.POINTER(vp)]
+        L.mcpd_batch_run.argtypes = [vp, C.c_uint64, vp, vp, vp, vp]
+        L.mcpd_batch_tune.argtypes = [vp, C.c_uint64, vp, C.c_uint32, vp]
+        L.mcpd_batch_config.argtypes = [vp, vp, vp, vp, vp]
+        L.mcpd_batch_buckets.argtypes = [vp, C.c_int32, C.c_uint32, vp, vp]
+        L.mcpd_batch_slot_records.argtypes = [vp, C.c_int32, vp, vp]
+        L.mcpd_batch_destroy.argtypes = [vp]
+        L.mcpd_batch_destroy.restype = None
+        L.mcpd_run_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_uint64, C.POINTER(RunOpts), vp, vp,
+                                     vp, vp]
         L.mcpd_strerror.argtypes = [C.c_int]
         L.mcpd_strerror.restype = C.c_char_p
         L.mcpd_last_error.argtypes = []
@@ -188,6 +208,94 @@ def mcpd_run_unbiased(h, n, budget, slots, k, m, seed=0, slot_records=False, buc
 def mcpd_destroy(h):
     if h:
         load().mcpd_destroy(h)
+
+
+def _ptr_array(arrays):
+    return (C.c_void_p * len(arrays))(*[a.ctypes.data for a in arrays])
+
+
+class Batch:
+    """Many instances in one persistent launch (mcpd_batch_*).
+
+    ``params`` holds (budget, slots, k, m) per instance.  Instance i draws its
+    random numbers with g = instance_id + i."""
+
+    def __init__(self, decoders, params, stream: Optional[int] = None, **opt):
+        self.decoders = list(decoders)   # keeps the instances alive
+        self.count = len(self.decoders)
+        if len(params) != self.count:
+            raise ValueError("one (budget, slots, k, m) per instance")
+        self.budget = np.array([p[0] for p in params], np.uint64)
+        self.slots = np.array([p[1] for p in params], np.uint32)
+        self.k = np.array([p[2] for p in params], np.uint32)
+        self.m = np.array([p[3] for p in params], np.uint32)
+        self.opts = run_opts(**opt)
+        insts = (C.c_void_p * self.count)(*[d.h.value for d in self.decoders])
+        h = C.c_void_p()
+        _check(load().mcpd_batch_create(insts, self.count, _p(self.budget), _p(self.slots), _p(self.k),
+                                        _p(self.m), C.byref(self.opts),
+                                        C.c_void_p(stream) if stream else None, C.byref(h)),
+               "mcpd_batch_create")
+        self.h = h
+
+    def run(self, seed=0, outputs=True):
+        """Returns a list of dict(marginals, stderr, hist, stats) per instance."""
+        n = [d.n for d in self.decoders]
+        hb = self.opts.hist_bins
+        marg = [np.zeros(x) for x in n] if outputs else None
+        se = [np.zeros(x) for x in n] if outputs else None
+        hist = [np.zeros(hb, np.uint64) for _ in n]
+        st = (RunStats * self.count)()
+        _check(load().mcpd_batch_run(self.h, seed, _ptr_array(marg) if outputs else None,
+                                     _ptr_array(se) if outputs else None, _ptr_array(hist), st),
+               "mcpd_batch_run")
+        out = []
+        for i in range(self.count):
+            r = dict(hist=hist[i], stats=st[i].as_dict())
+            if outputs:
+                r.update(marginals=marg[i], stderr=se[i])
+            out.append(r)
+        return out
+
+    def tune(self, seed=0):
+        cap = 32
+        ent = (TuneEntry * cap)()
+        cnt = C.c_uint32()
+        _check(load().mcpd_batch_tune(self.h, seed, ent, cap, C.byref(cnt)), "mcpd_batch_tune")
+        return [dict(wg_per_cu=int(e.wg_per_cu), ticket_slots=int(e.ticket_slots), ms=float(e.ms))
+                for e in ent[:cnt.value]]
+
+    def config(self):
+        wg, ts, lanes = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        place = np.zeros(self.count, np.uint32)
+        _check(load().mcpd_batch_config(self.h, C.byref(wg), C.byref(ts), C.byref(lanes), _p(place)),
+               "mcpd_batch_config")
+        return dict(wg_per_cu=wg.value, ticket_slots=ts.value, lanes=lanes.value, placement=place)
+
+    def buckets(self, i, rows):
+        n = self.decoders[i].n
+        b1 = np.zeros((rows, n), np.int64)
+        b2 = np.zeros((rows, n, 2), np.uint64)
+        _check(load().mcpd_batch_buckets(self.h, i, rows, _p(b1), _p(b2)), "mcpd_batch_buckets")
+        return b1, b2
+
+    def slot_records(self, i):
+        P = int(self.slots[i])
+        ns = np.zeros(P, np.uint32)
+        su = np.zeros(P, np.uint64)
+        _check(load().mcpd_batch_slot_records(self.h, i, _p(ns), _p(su)), "mcpd_batch_slot_records")
+        return ns, su
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().mcpd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Decoder:

@@ -23,22 +23,24 @@ def declared_functions():
 def test_library_exports_every_declared_symbol():
     L = N.load()
     names = declared_functions()
-    assert len(names) >= 9
+    assert len(names) >= 17
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
-    assert set(names) <= set(N.EXPORTS) | set(names)
+    assert set(names) == set(N.EXPORTS)
 
 
 def test_struct_layouts_match_header():
-    # mcpd_run_opts: u64, 8 x u32, 4 pointers, u32 (+ pad); mcpd_run_stats: 13 x u64, 2 x u32, double
-    assert C.sizeof(N.RunOpts) == 8 + 8 * 4 + 4 * 8 + 8
-    assert C.sizeof(N.RunStats) == 13 * 8 + 2 * 4 + 8
+    # mcpd_run_opts: u64, 12 x u32, 4 pointers; mcpd_run_stats: 14 x u64, 2 x u32, double
+    assert C.sizeof(N.RunOpts) == 8 + 12 * 4 + 4 * 8
+    assert C.sizeof(N.RunStats) == 14 * 8 + 2 * 4 + 8
+    assert C.sizeof(N.TuneEntry) == 16
 
 
 def test_run_opts_defaults():
     o = N.run_opts()
     assert (o.max_steps, o.refill, o.strict_cap, o.hist_bins, o.hist_width, o.u_hi_bits,
-            o.instance_id, o.plan, o.wg_per_cu) == (0, 1, 0, 64, 0, 32, 0, 0, 0)
+            o.instance_id, o.plan, o.wg_per_cu, o.ticket_slots, o.use_graph,
+            o.keep_slot_records) == (0, 1, 0, 64, 0, 32, 0, 0, 0, 0, 1, 0)
 
 
 def test_strerror_names_codes():
