@@ -1,8 +1,8 @@
 """Build the HIP library (libmcpd.so) in-tree for gfx950 with hipcc.
 
 The sampler is compiled once per clone-row format (each instantiation is a
-large kernel) and once for its dispatcher, in parallel, then linked with the
-host side of the C ABI.
+large kernel) and once for its dispatcher, in parallel with the kernels of
+the learned weights and the host side of the C ABI, then linked.
 """
 
 from __future__ import annotations
@@ -38,7 +38,8 @@ def hipcc() -> str:
 
 def jobs():
     """(source, extra flags, object name) of every compile step."""
-    out = [("mcpd_host.cpp", [], "host.o"), ("mcpd_sampler.hip", [], "sampler.o")]
+    out = [("mcpd_host.cpp", [], "host.o"), ("mcpd_sampler.hip", [], "sampler.o"),
+           ("mcpd_mlp.hip", [], "mlp.o"), ("mcpd_mlp_host.cpp", [], "mlp_host.o")]
     out += [("mcpd_sampler.hip", [f"-DMCPD_FMT={f}"], f"sampler_f{f}.o") for f in range(N_FORMATS)]
     return out
 

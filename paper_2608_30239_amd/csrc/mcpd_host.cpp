@@ -33,27 +33,7 @@
 #pragma GCC visibility pop
 #include "mcpd_device.h"
 
-namespace mcpd {
-namespace host {
-struct Launch;
-}
-}  // namespace mcpd
-
-struct mcpd_instance {
-    int32_t n = 0, m = 0, dmax = 0, abits = 1;
-    uint32_t thr_len = 1;
-    double fp = 0, fn = 0, q = 0;
-    std::vector<int32_t> row_ptr, pool_idx;
-    std::vector<uint8_t> y;
-    std::vector<uint64_t> mass;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    int cus = 0;
-    uint32_t *d_alias = nullptr;
-    uint64_t *d_thr = nullptr;
-    uint32_t *d_rows[mcpd::FMT_COUNT] = {};   // clone rows per format, built when first needed
-    mcpd::host::Launch *single = nullptr;      // workspace of mcpd_run_unbiased
-};
+#include "mcpd_internal.h"
 
 namespace mcpd {
 namespace host {
@@ -70,12 +50,6 @@ int hip_fail(hipError_t e, const char *what)
 {
     return fail(MCPD_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr)                                   \
-    do {                                                \
-        hipError_t e_ = (expr);                         \
-        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
-    } while (0)
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -772,6 +746,10 @@ void release(mcpd_instance *I)
     }
     I->d_alias = nullptr;
     I->d_thr = nullptr;
+    for (void *p : {(void *)I->d_row_ptr, (void *)I->d_pool_idx, (void *)I->d_pool_size, (void *)I->d_y})
+        if (p) (void)hipFree(p);
+    I->d_row_ptr = I->d_pool_idx = I->d_pool_size = nullptr;
+    I->d_y = nullptr;
 }
 
 }  // namespace host

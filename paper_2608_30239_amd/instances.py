@@ -219,3 +219,15 @@ def uneven_batch(count: int = 256, seed: int = 4, n_lo: int = 200, n_hi: int = 2
         insts.append(inst)
         params.append(RunParams(budget=budget, slots=slots, k=k, m=l, seed=0))
     return insts, params
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Initial FP32 parameters of the 8-64-64-1 selection-weight network,
+    flat in the layout W1 [64][8], b1 [64], W2 [64][64], b2 [64], W3 [64], b3:
+    every weight and bias of a layer uniform in +-1/sqrt(fan_in)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, count in ((8, 64 * 8), (8, 64), (64, 64 * 64), (64, 64), (64, 64), (64, 1)):
+        b = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-b, b, count))
+    return np.concatenate(parts).astype(np.float32)

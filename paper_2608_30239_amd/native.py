@@ -77,8 +77,20 @@ class TuneEntry(C.Structure):
 EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_create", "mcpd_set_weights",
            "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_destroy", "mcpd_batch_create",
            "mcpd_batch_run", "mcpd_batch_tune", "mcpd_batch_config", "mcpd_batch_buckets",
-           "mcpd_batch_slot_records", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_strerror",
+           "mcpd_batch_slot_records", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_features",
+           "mcpd_mlp_create", "mcpd_mlp_get_params", "mcpd_mlp_set_params", "mcpd_mlp_forward",
+           "mcpd_mlp_set_training_rows", "mcpd_mlp_set_training_data", "mcpd_mlp_loss_grad",
+           "mcpd_mlp_train", "mcpd_set_learned_weights", "mcpd_mlp_destroy", "mcpd_strerror",
            "mcpd_last_error")
+
+MLP_FEATURES = 8
+MLP_HIDDEN = 64
+MLP_PARAMS = 4801
+
+
+class AdamW(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float)]
 
 _lock = threading.Lock()
 _lib = None
@@ -118,6 +130,18 @@ def load(path: Optional[str] = None):
         L.mcpd_batch_destroy.restype = None
         L.mcpd_run_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_uint64, C.POINTER(RunOpts), vp, vp,
                                      vp, vp]
+        L.mcpd_features.argtypes = [vp, vp]
+        L.mcpd_mlp_create.argtypes = [vp, vp, C.POINTER(vp)]
+        L.mcpd_mlp_get_params.argtypes = [vp, vp, vp]
+        L.mcpd_mlp_set_params.argtypes = [vp, vp]
+        L.mcpd_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
+        L.mcpd_mlp_set_training_rows.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int32, C.c_double, C.c_double]
+        L.mcpd_mlp_set_training_data.argtypes = [vp, vp, vp, C.c_int32, C.c_double, C.c_double]
+        L.mcpd_mlp_loss_grad.argtypes = [vp, vp, vp]
+        L.mcpd_mlp_train.argtypes = [vp, C.c_int32, C.POINTER(AdamW), vp]
+        L.mcpd_set_learned_weights.argtypes = [vp, vp, C.c_double, vp]
+        L.mcpd_mlp_destroy.argtypes = [vp]
+        L.mcpd_mlp_destroy.restype = None
         L.mcpd_strerror.argtypes = [C.c_int]
         L.mcpd_strerror.restype = C.c_char_p
         L.mcpd_last_error.argtypes = []
@@ -289,6 +313,84 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             load().mcpd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mcpd_features(dec):
+    X = np.zeros((dec.n, MLP_FEATURES), np.float32)
+    _check(load().mcpd_features(dec.h, _p(X)), "mcpd_features")
+    return X
+
+
+class Mlp:
+    """The selection-weight network (mcpd_mlp_*): FP32 master parameters,
+    BF16 working copy, training and inference on the device."""
+
+    def __init__(self, params, stream: Optional[int] = None):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.shape != (MLP_PARAMS,):
+            raise ValueError(f"need {MLP_PARAMS} parameters")
+        h = C.c_void_p()
+        _check(load().mcpd_mlp_create(_p(p), C.c_void_p(stream) if stream else None, C.byref(h)),
+               "mcpd_mlp_create")
+        self.h = h
+
+    def params(self):
+        master = np.zeros(MLP_PARAMS, np.float32)
+        bf16 = np.zeros(MLP_PARAMS, np.uint16)
+        _check(load().mcpd_mlp_get_params(self.h, _p(master), _p(bf16)), "mcpd_mlp_get_params")
+        return master, bf16
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        _check(load().mcpd_mlp_set_params(self.h, _p(p)), "mcpd_mlp_set_params")
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, np.float32)
+        g = np.zeros(X.shape[0], np.float32)
+        _check(load().mcpd_mlp_forward(self.h, _p(X), X.shape[0], _p(g)), "mcpd_mlp_forward")
+        return g
+
+    def set_training_rows(self, X, p_hat, seg_ptr, lam=1.0, eps=1e-3):
+        X = np.ascontiguousarray(X, np.float32)
+        p_hat = np.ascontiguousarray(p_hat, np.float64)
+        seg = np.ascontiguousarray(seg_ptr, np.int64)
+        _check(load().mcpd_mlp_set_training_rows(self.h, _p(X), _p(p_hat), X.shape[0], _p(seg), len(seg) - 1,
+                                                 lam, eps), "mcpd_mlp_set_training_rows")
+
+    def set_training_data(self, decoders, p_hats, lam=1.0, eps=1e-3):
+        ph = [np.ascontiguousarray(p, np.float64) for p in p_hats]
+        insts = (C.c_void_p * len(decoders))(*[d.h.value for d in decoders])
+        _check(load().mcpd_mlp_set_training_data(self.h, insts, _ptr_array(ph), len(decoders), lam, eps),
+               "mcpd_mlp_set_training_data")
+
+    def loss_grad(self):
+        loss = C.c_double()
+        grad = np.zeros(MLP_PARAMS, np.float32)
+        _check(load().mcpd_mlp_loss_grad(self.h, C.byref(loss), _p(grad)), "mcpd_mlp_loss_grad")
+        return loss.value, grad
+
+    def train(self, steps, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        hp = AdamW(lr, beta1, beta2, eps, weight_decay)
+        hist = np.zeros(max(steps, 1))
+        _check(load().mcpd_mlp_train(self.h, steps, C.byref(hp), _p(hist)), "mcpd_mlp_train")
+        return hist[:steps]
+
+    def apply(self, dec, alpha=0.5):
+        """Set dec's selection weights from the network; returns w."""
+        w = np.zeros(dec.n)
+        _check(load().mcpd_set_learned_weights(dec.h, self.h, alpha, _p(w)), "mcpd_set_learned_weights")
+        return w
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().mcpd_mlp_destroy(self.h)
             self.h = None
 
     def __del__(self):

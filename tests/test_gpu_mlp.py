@@ -1,0 +1,169 @@
+"""GPU parity of the learned-weights kernels (features, forward, loss and
+gradient, AdamW, weights from the network) against the FP64 oracle in
+oracle/mlp_oracle.py.
+
+Tolerances follow from the arithmetic: the kernels accumulate in FP32
+(unit roundoff 2^-24) over at most 64 terms per unit, and over the rows of
+a chunk then over blocks for the gradient; the oracle is FP64.  Features are
+FP64 values rounded once to FP32.  BF16 roundings and the integer masses
+derived from given weights are compared exactly."""
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as MO
+from oracle import oracle as O
+from paper_2608_30239_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+N = pytest.importorskip("paper_2608_30239_amd.native")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    N.load()
+
+
+def bf16_bits(x32):
+    return (MO.bf16_round(x32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+def some_instances():
+    hand = I.from_dense("hand", np.array([[1, 0, 0, 1], [1, 1, 0, 0], [0, 1, 1, 1]], np.uint8),
+                        np.array([1, 0, 1], np.uint8), 0.05, 0.1, 0.2)
+    tiny, _ = I.tiny_plain()
+    paper, _ = I.paper_shaped()
+    big = I.make_instance("u3000", 3000, 225, (3, 7), 5, 0.12, 0.07, prior=5 / 3000, seed=9)
+    eq = I.identity_instance(5, 0.1, 0.1, 0.2)
+    eq.y[:] = 0
+    return [hand, tiny, paper, big, eq]
+
+
+@pytest.mark.parametrize("k", range(5))
+def test_features_match_oracle(k):
+    inst = some_instances()[k]
+    dec = N.Decoder(inst)
+    try:
+        X = N.mcpd_features(dec)
+    finally:
+        dec.close()
+    ref = MO.features(inst)
+    assert np.array_equal(X, ref.astype(np.float32))
+
+
+def test_forward_and_bf16_copy():
+    theta = I.mlp_init(1)
+    net = N.Mlp(theta)
+    try:
+        master, bf = net.params()
+        assert np.array_equal(master, theta)
+        assert np.array_equal(bf, bf16_bits(theta))
+        rng = np.random.default_rng(2)
+        for rows in (1, 255, 256, 257, 10007):
+            X = rng.uniform(0, 2, (rows, 8)).astype(np.float32)
+            g = net.forward(X)
+            ref, c = MO.forward(MO.bf16_round(theta), X.astype(np.float64))
+            # FP32 accumulation over <= 65 terms per unit: a few hundred units
+            # of 2^-24 of the magnitudes that flow into g
+            W3 = MO.split(MO.bf16_round(theta).astype(np.float64))[4]
+            scale = 1.0 + np.abs(c["h2"]) @ np.abs(W3) + np.abs(ref)
+            assert np.all(np.abs(g - ref) <= 1e-5 * scale), rows
+    finally:
+        net.close()
+
+
+def _training_rows(seed=3, sizes=(1, 255, 256, 257, 3000)):
+    rng = np.random.default_rng(seed)
+    rows = sum(sizes)
+    X = rng.uniform(0, 1.5, (rows, 8)).astype(np.float32)
+    p_hat = rng.uniform(-0.05, 1.05, rows)
+    seg = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return X, p_hat, seg
+
+
+@pytest.mark.parametrize("lam,eps", [(1.0, 1e-3), (0.5, 1e-2), (2.0, 1e-4)])
+def test_loss_and_gradient_match_oracle(lam, eps):
+    theta = I.mlp_init(4)
+    X, p_hat, seg = _training_rows()
+    net = N.Mlp(theta)
+    try:
+        net.set_training_rows(X, p_hat, seg, lam, eps)
+        loss, grad = net.loss_grad()
+    finally:
+        net.close()
+    tb = MO.bf16_round(theta).astype(np.float64)
+    g, _ = MO.forward(tb, X.astype(np.float64))
+    t = MO.targets(p_hat, seg, lam, eps)
+    ref_loss, dg = MO.loss_and_dg(g, t, seg)
+    ref_grad = MO.backward(tb, X.astype(np.float64), dg)
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
+    assert np.max(np.abs(grad - ref_grad)) <= 1e-4 * np.max(np.abs(ref_grad))
+
+
+def test_single_row_segments_have_zero_loss():
+    theta = I.mlp_init(5)
+    X, p_hat, _ = _training_rows(sizes=(1, 1, 1))
+    net = N.Mlp(theta)
+    try:
+        net.set_training_rows(X, p_hat, np.array([0, 1, 2, 3]))
+        loss, grad = net.loss_grad()
+    finally:
+        net.close()
+    assert abs(loss) < 1e-12 and np.max(np.abs(grad)) < 1e-12
+
+
+def test_adamw_steps_match_oracle():
+    theta = I.mlp_init(6)
+    X, p_hat, seg = _training_rows(seed=7)
+    hp = dict(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-6, weight_decay=0.05)
+    net = N.Mlp(theta)
+    try:
+        net.set_training_rows(X, p_hat, seg)
+        th = theta.astype(np.float64)
+        m = np.zeros_like(th)
+        v = np.zeros_like(th)
+        for step in (1, 2, 3):
+            _, grad = net.loss_grad()
+            net.train(1, **hp)
+            master, bf = net.params()
+            th, m, v = MO.adamw_step(th, m, v, grad.astype(np.float64), step, hp["lr"], hp["beta1"],
+                                     hp["beta2"], hp["eps"], hp["weight_decay"])
+            assert np.max(np.abs(master - th)) <= 1e-6 * (1 + np.max(np.abs(th)))
+            assert np.array_equal(bf, bf16_bits(master))
+            th = master.astype(np.float64)   # continue from the device state
+    finally:
+        net.close()
+
+
+def test_training_lowers_the_loss():
+    theta = I.mlp_init(8)
+    X, p_hat, seg = _training_rows(seed=9, sizes=(700, 900, 1300))
+    net = N.Mlp(theta)
+    try:
+        net.set_training_rows(X, p_hat, seg, 1.0, 1e-3)
+        hist = net.train(150, lr=3e-3)
+        loss, _ = net.loss_grad()
+    finally:
+        net.close()
+    assert hist[0] > 0 and loss < 0.8 * hist[0]
+    assert np.all(np.isfinite(hist))
+
+
+def test_learned_weights_match_oracle_and_feed_the_sampler():
+    inst, rp = I.paper_shaped()
+    theta = I.mlp_init(10)
+    net = N.Mlp(theta)
+    dec = N.Decoder(inst)
+    try:
+        X = N.mcpd_features(dec)
+        w = net.apply(dec, alpha=0.5)
+        _, mass = dec.weights()
+    finally:
+        dec.close()
+        net.close()
+    g, _ = MO.forward(MO.bf16_round(theta), X.astype(np.float64))
+    ref = MO.selection_weights(g, 0.5)
+    assert np.max(np.abs(w - ref) / ref) <= 1e-5
+    assert w.min() >= 0.5 / inst.n and abs(w.sum() - 1) < 1e-12
+    assert np.array_equal(mass, O.quantize(w))
