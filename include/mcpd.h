@@ -248,20 +248,25 @@ int mcpd_run_batch(mcpd_instance *const *insts, int32_t count, const uint64_t *b
  * (Theorem 1), so they may be chosen by a small network from per-clone
  * features; the score weights stay the fallback.
  *
+ * Base logits: c_i = tau_w (s_i - s_max), the log-weights of the softmax
+ * part of the score weights (s, tau_w as in mcpd_score_weights; c = 0 if all
+ * scores are equal).
  * Features (8 per clone, FP32): #positive pools / 8, #negative pools / 8,
  * mean size of the positive pools / 64, mean size of the negative pools / 64,
- * smallest positive pool / 64 (the three are 0 without such pools),
- * (s_i - s_min) / (s_max - s_min) with s the score of mcpd_score_weights (0
- * if all equal), 10 fp, 10 fn.
- * Network: g = W3 relu(W2 relu(W1 x + b1) + b2) + b3, widths 8-64-64-1,
+ * smallest positive pool / 64 (the three are 0 without such pools), c_i / 16,
+ * 10 fp, 10 fn.
+ * Network: f = W3 relu(W2 relu(W1 x + b1) + b2) + b3, widths 8-64-64-1,
  * MCPD_MLP_PARAMS parameters laid out flat as W1 [64][8] (out, in), b1 [64],
  * W2 [64][64], b2 [64], W3 [64], b3.  An FP32 master copy is trained; the
  * kernels compute in FP32 with its BF16 rounding (nearest, ties to even).
- * Weights: w = (1 - alpha) softmax(g) + alpha / n (FP64 softmax on the host).
- * Training target of an instance: t_i ~ (u_i (1-u_i))^(lambda/2) + eps,
- * u = clip(p_hat, 0, 1) from the method's own marginals; loss = mean over
- * instances of KL(t || softmax(g)); optimiser AdamW (decoupled weight decay
- * on every parameter).
+ * Weights: w = (1 - alpha) softmax(c + f) + alpha / n (FP64 softmax on the
+ * host): a network that outputs 0 gives back the score weights.
+ * Training target of an instance: t_i ~ exp(beta c_i) (u_i + eps)^gamma,
+ * u = clip(v, 0, 1) for a per-clone signal v from the method's own outputs
+ * (for instance its marginals, or the per-update scales SE_j sqrt(w_j) of
+ * its standard errors over their maximum); loss = mean over
+ * instances of KL(t || softmax(c + f)); optimiser AdamW (decoupled weight
+ * decay on every parameter).
  * ------------------------------------------------------------------------ */
 #define MCPD_MLP_FEATURES 8
 #define MCPD_MLP_HIDDEN 64
@@ -273,9 +278,10 @@ typedef struct mcpd_adamw {
     float lr, beta1, beta2, eps, weight_decay;
 } mcpd_adamw;
 
-/* Features of every clone: out host [n * 8] (row-major), computed on the
- * device.  Errors: MCPD_EINVAL, MCPD_ENOMEM, MCPD_EDEVICE. */
-int mcpd_features(mcpd_instance *inst, float *out);
+/* Features of every clone: out host [n * 8] (row-major) and base logits
+ * base_out host [n] (may be NULL), computed on the device.
+ * Errors: MCPD_EINVAL, MCPD_ENOMEM, MCPD_EDEVICE. */
+int mcpd_features(mcpd_instance *inst, float *out, double *base_out);
 
 /* Create a network from FP32 master parameters (host [MCPD_MLP_PARAMS]).
  * hip_stream as in mcpd_create.  Errors: MCPD_EINVAL (null or non-finite
@@ -289,20 +295,22 @@ int mcpd_mlp_get_params(const mcpd_mlp *mlp, float *master, uint16_t *bf16);
 /* Replace the master copy (host [MCPD_MLP_PARAMS]); resets the optimiser. */
 int mcpd_mlp_set_params(mcpd_mlp *mlp, const float *master);
 
-/* Logits of `rows` feature rows: x host [rows * 8], g host [rows]. */
+/* Network outputs f of `rows` feature rows: x host [rows * 8], g host [rows]. */
 int mcpd_mlp_forward(mcpd_mlp *mlp, const float *x, int64_t rows, float *g);
 
-/* Training set from raw rows: x host [rows * 8], p_hat host [rows] (the
- * method's marginals), seg_ptr host [nseg + 1] with seg_ptr[0] = 0 and
- * seg_ptr[nseg] = rows, non-decreasing with non-empty segments (one per
- * instance); lambda >= 0, eps > 0.  Copied to the device. */
-int mcpd_mlp_set_training_rows(mcpd_mlp *mlp, const float *x, const double *p_hat, int64_t rows,
-                               const int64_t *seg_ptr, int32_t nseg, double lambda, double eps);
+/* Training set from raw rows: x host [rows * 8], base host [rows] (base
+ * logits, finite and <= 0), signal host [rows] (the per-clone signal v),
+ * seg_ptr host [nseg + 1] with seg_ptr[0] = 0 and seg_ptr[nseg] = rows,
+ * increasing (one non-empty segment per instance); beta, gamma >= 0,
+ * eps > 0.  Copied to the device. */
+int mcpd_mlp_set_training_rows(mcpd_mlp *mlp, const float *x, const double *base, const double *signal,
+                               int64_t rows, const int64_t *seg_ptr, int32_t nseg, double beta, double gamma,
+                               double eps);
 
 /* Training set from instances: their features (computed on the device) and
- * p_hat[i] host [n_i] for instance i. */
-int mcpd_mlp_set_training_data(mcpd_mlp *mlp, mcpd_instance *const *insts, const double *const *p_hat,
-                               int32_t count, double lambda, double eps);
+ * signal[i] host [n_i] (the signal v) for instance i. */
+int mcpd_mlp_set_training_data(mcpd_mlp *mlp, mcpd_instance *const *insts, const double *const *signal,
+                               int32_t count, double beta, double gamma, double eps);
 
 /* Loss over the training set and its gradient in the parameters (host
  * [MCPD_MLP_PARAMS] or NULL), for the current parameters. */
@@ -314,9 +322,10 @@ int mcpd_mlp_loss_grad(mcpd_mlp *mlp, double *loss, float *grad);
  * continues across calls until mcpd_mlp_set_params. */
 int mcpd_mlp_train(mcpd_mlp *mlp, int32_t steps, const mcpd_adamw *hp, double *loss_history);
 
-/* Set an instance's selection weights from the network: features, logits on
- * the device, then w = (1 - alpha) softmax(g) + alpha / n, 0 < alpha <= 1,
- * passed to mcpd_set_weights.  w_out host [n] or NULL receives w. */
+/* Set an instance's selection weights from the network: features, base
+ * logits and network outputs on the device, then w = (1 - alpha)
+ * softmax(c + f) + alpha / n, 0 < alpha <= 1, passed to mcpd_set_weights.
+ * w_out host [n] or NULL receives w. */
 int mcpd_set_learned_weights(mcpd_instance *inst, mcpd_mlp *mlp, double alpha, double *w_out);
 
 /* Release a network (NULL is a no-op). */

@@ -10,21 +10,29 @@ start, so that the Gibbs kernel keeps pi invariant and the coupled estimator
 stays unbiased: Proposition 1, Theorem 1, Assumption 1; the floor is the one
 of the score weights, Section "Score-Weighted Update Gibbs Sampler"):
 
+  base logits: c_i = tau_w (s_i - s_max), the log-weights of the softmax
+    part of the paper's score weights (s_i = sum_j d_j a_j, tau_w =
+    log(100 n) / (s_max - s_min), 0 if all scores are equal);
   features x_i (8 per clone), from the design and the outcomes only:
     x0 = #positive pools of i / 8          x1 = #negative pools of i / 8
     x2 = mean size of its positive pools / 64 (0 if none)
     x3 = mean size of its negative pools / 64 (0 if none)
     x4 = smallest size of its positive pools / 64 (0 if none)
-    x5 = (s_i - s_min) / (s_max - s_min), s the paper's score (0 if equal)
-    x6 = 10 fp                            x7 = 10 fn
-  network: g = W3 relu(W2 relu(W1 x + b1) + b2) + b3, widths 8-64-64-1,
+    x5 = c_i / 16, the normalised score     x6 = 10 fp      x7 = 10 fn
+  network: f = W3 relu(W2 relu(W1 x + b1) + b2) + b3, widths 8-64-64-1,
     4801 parameters, used through their BF16 roundings (round to nearest,
     ties to even), the FP32 master copy being what the optimiser updates;
-  weights: w = (1 - alpha) softmax(g) + alpha / n;
-  training target per instance: t_i ~ (u_i (1 - u_i))^(lambda/2) + eps with
-    u = clip(p_hat, 0, 1), normalised over the instance; the loss is the mean
-    over instances of KL(t || softmax(g)); the optimiser is AdamW
-    (Loshchilov and Hutter, decoupled weight decay) on every parameter.
+    the logits are c + f, so a network that outputs 0 gives back the
+    score weights exactly;
+  weights: w = (1 - alpha) softmax(c + f) + alpha / n;
+  training target per instance: t_i ~ exp(beta c_i) (u_i + eps)^gamma with
+    u = clip(v, 0, 1) for a per-clone signal v taken from the method's own
+    outputs (its marginals, or the per-update scales SE_j sqrt(w_j) of its
+    standard errors, over their maximum), normalised over the instance
+    (beta = 1, gamma = 0 is the score softmax itself); the loss is
+    the mean over instances of KL(t || softmax(c + f)); the optimiser is
+    AdamW (Loshchilov and Hutter, decoupled weight decay) on every
+    parameter.
 
 Parameter layout (flat, 4801): W1 [64][8] (out, in), b1 [64], W2 [64][64],
 b2 [64], W3 [64], b3 [1].
@@ -71,6 +79,14 @@ def bf16_round(a):
     return (r & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.float32)
 
 
+def base_logits(inst):
+    """c_i = tau_w (s_i - s_max) with the paper's tau_w (0 if all equal)."""
+    s, _ = O.score_weights(inst)
+    smin, smax = float(np.min(s)), float(np.max(s))
+    tau = np.log(100.0 * inst.n) / (smax - smin) if smax > smin else 0.0
+    return tau * (s - smax)
+
+
 def features(inst):
     """[n, 8] float64 features of every clone (see the module docstring)."""
     n, m = inst.n, inst.m
@@ -78,8 +94,7 @@ def features(inst):
     size = np.zeros(m, np.int64)
     for j in pi:
         size[j] += 1
-    s, _ = O.score_weights(inst)
-    smin, smax = float(np.min(s)), float(np.max(s))
+    c = base_logits(inst)
     X = np.zeros((n, F))
     for i in range(n):
         pools = pi[rp[i]:rp[i + 1]]
@@ -90,7 +105,7 @@ def features(inst):
         X[i, 2] = (sum(pos) / len(pos)) / 64.0 if pos else 0.0
         X[i, 3] = (sum(neg) / len(neg)) / 64.0 if neg else 0.0
         X[i, 4] = min(pos) / 64.0 if pos else 0.0
-        X[i, 5] = (s[i] - smin) / (smax - smin) if smax > smin else 0.0
+        X[i, 5] = c[i] / 16.0
         X[i, 6] = 10.0 * inst.fp
         X[i, 7] = 10.0 * inst.fn
     return X
@@ -109,24 +124,27 @@ def forward(theta_bf16, X):
     return g, dict(z1=z1, h1=h1, z2=z2, h2=h2)
 
 
-def targets(p_hat, seg_ptr, lam, eps):
-    """t per instance segment: ((u (1-u))^(lam/2) + eps) / sum, u = clip(p_hat, 0, 1)."""
-    u = np.clip(np.asarray(p_hat, np.float64), 0.0, 1.0)
-    raw = (u * (1.0 - u)) ** (lam / 2.0) + eps
+def targets(signal, base, seg_ptr, beta, gamma, eps):
+    """t per instance segment: exp(beta c) (u + eps)^gamma / sum, with
+    u = clip(signal, 0, 1) and c the base logits."""
+    u = np.clip(np.asarray(signal, np.float64), 0.0, 1.0)
+    raw = np.exp(beta * np.asarray(base, np.float64)) * (u + eps) ** gamma
     t = np.empty_like(raw)
     for a, b in zip(seg_ptr[:-1], seg_ptr[1:]):
         t[a:b] = raw[a:b] / raw[a:b].sum()
     return t
 
 
-def loss_and_dg(g, t, seg_ptr):
-    """Mean over segments of KL(t || softmax(g)) and its gradient in g:
-    (softmax(g) - t) / #segments on each segment (t sums to 1 on it)."""
+def loss_and_dg(f, base, t, seg_ptr):
+    """Mean over segments of KL(t || softmax(c + f)) and its gradient in the
+    network output f: (softmax(c + f) - t) / #segments on each segment (t
+    sums to 1 on it)."""
     S = len(seg_ptr) - 1
     loss = 0.0
-    dg = np.zeros_like(np.asarray(g, np.float64))
+    g = np.asarray(base, np.float64) + np.asarray(f, np.float64)
+    dg = np.zeros_like(g)
     for a, b in zip(seg_ptr[:-1], seg_ptr[1:]):
-        ga = np.asarray(g[a:b], np.float64)
+        ga = g[a:b]
         mx = ga.max()
         e = np.exp(ga - mx)
         Z = e.sum()
@@ -167,8 +185,8 @@ def adamw_step(theta, m, v, grad, step, lr, beta1, beta2, eps, wd):
     return theta, m, v
 
 
-def selection_weights(g, alpha=0.5):
-    """w = (1 - alpha) softmax(g) + alpha / n."""
-    g = np.asarray(g, np.float64)
+def selection_weights(f, base, alpha=0.5):
+    """w = (1 - alpha) softmax(c + f) + alpha / n."""
+    g = np.asarray(base, np.float64) + np.asarray(f, np.float64)
     e = np.exp(g - g.max())
     return (1.0 - alpha) * e / e.sum() + alpha / len(g)

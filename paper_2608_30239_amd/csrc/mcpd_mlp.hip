@@ -1,8 +1,9 @@
-// Kernels of the learned selection weights: per-clone features, the
-// 8-64-64-1 ReLU network (BF16 weights, FP32 arithmetic), the per-instance
-// softmax-KL loss and its gradient, the backward pass with a fixed-order
-// reduction of the parameter gradient, and AdamW on the FP32 master copy
-// with the BF16 working copy rewritten after each step.
+// Kernels of the learned selection weights: per-clone features and base
+// logits (the log-weights of the score softmax), the 8-64-64-1 ReLU network
+// (BF16 weights, FP32 arithmetic) whose output is added to the base logits,
+// the per-instance softmax-KL loss and its gradient, the backward pass with
+// a fixed-order reduction of the parameter gradient, and AdamW on the FP32
+// master copy with the BF16 working copy rewritten after each step.
 //
 // Selection weights only have to be positive and fixed before the chains
 // start for the Gibbs kernel to keep pi invariant (Proposition 1) and for
@@ -56,7 +57,8 @@ __global__ void pool_size_kernel(const int32_t *pool_idx, int64_t nnz, int32_t *
 }
 
 // Raw features of each clone and its score s_i = sum_j d_j a_j (FP64, pools
-// in ascending order, starting from 0).
+// in ascending order, starting from 0), the paper's score of
+// Section "Score-Weighted Update Gibbs Sampler".
 __global__ void features_raw_kernel(const int32_t *row_ptr, const int32_t *pool_idx, const uint8_t *y,
                                     const int32_t *size, int32_t n, double a_pos, double a_neg, float fp10,
                                     float fn10, double *score, float *X)
@@ -91,9 +93,10 @@ __global__ void features_raw_kernel(const int32_t *row_ptr, const int32_t *pool_
     x[7] = fn10;
 }
 
-// One block: min and max of the scores (exact in any order), then
-// x5 = (s - s_min) / (s_max - s_min), 0 if all scores are equal.
-__global__ void features_norm_kernel(const double *score, int32_t n, float *X)
+// One block: min and max of the scores (exact in any order), then the base
+// logits c_i = tau_w (s_i - s_max), tau_w = log(100 n) / (s_max - s_min) (0
+// if all scores are equal), written over the scores, and x5 = c_i / 16.
+__global__ void features_norm_kernel(double *score, int32_t n, double log100n, float *X)
 {
     __shared__ double smin[256], smax[256];
     double lo = INFINITY, hi = -INFINITY;
@@ -113,8 +116,12 @@ __global__ void features_norm_kernel(const double *score, int32_t n, float *X)
     }
     lo = smin[0];
     hi = smax[0];
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x)
-        X[(size_t)i * F + 5] = hi > lo ? (float)((score[i] - lo) / (hi - lo)) : 0.f;
+    const double tau = hi > lo ? log100n / (hi - lo) : 0.0;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double c = tau * (score[i] - hi);
+        score[i] = c;
+        X[(size_t)i * F + 5] = (float)(c / 16.0);
+    }
 }
 
 // ----------------------------------------------------------------- forward
@@ -162,9 +169,10 @@ __global__ void __launch_bounds__(ROWS) forward_kernel(const uint16_t *wb, const
 
 // -------------------------------------------------------------------- loss
 
-// One block per instance segment [seg_ptr[s], seg_ptr[s+1]):
-//   t_i = ((u_i (1-u_i))^(lambda/2) + eps) / sum, u = clip(p_hat, 0, 1)
-//   p = softmax(g), loss_s = sum t (log t - log p), dg = (p - t) / S.
+// One block per instance segment [seg_ptr[s], seg_ptr[s+1]), with base
+// logits c and network outputs f:
+//   t_i = exp(beta c_i) (u_i + eps)^gamma / sum, u = clip(signal, 0, 1)
+//   p = softmax(c + f), loss_s = sum t (log t - log p), df = (p - t) / S.
 // Reductions in FP64 over a fixed tree.
 __device__ double block_sum(double v, double *sh)
 {
@@ -192,34 +200,34 @@ __device__ double block_max(double v, double *sh)
     return out;
 }
 
-__device__ __forceinline__ double target_raw(double p, double half_lambda, double eps)
+__device__ __forceinline__ double target_raw(double p, double c, double beta, double gamma, double eps)
 {
     const double u = p < 0.0 ? 0.0 : (p > 1.0 ? 1.0 : p);
-    return pow(u * (1.0 - u), half_lambda) + eps;
+    return exp(beta * c) * pow(u + eps, gamma);
 }
 
-__global__ void __launch_bounds__(256) loss_kernel(const float *g, const double *p_hat, const int64_t *seg_ptr,
-                                                   int32_t nseg, double half_lambda, double eps, double *seg_loss,
-                                                   float *dg)
+__global__ void __launch_bounds__(256) loss_kernel(const float *f, const double *base, const double *signal,
+                                                   const int64_t *seg_ptr, int32_t nseg, double beta, double gamma,
+                                                   double eps, double *seg_loss, float *dg)
 {
     __shared__ double sh[256];
     const int s = blockIdx.x;
     const int64_t a = seg_ptr[s], b = seg_ptr[s + 1];
     double mx = -INFINITY, tsum = 0.0;
     for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
-        mx = fmax(mx, (double)g[i]);
-        tsum += target_raw(p_hat[i], half_lambda, eps);
+        mx = fmax(mx, base[i] + (double)f[i]);
+        tsum += target_raw(signal[i], base[i], beta, gamma, eps);
     }
     mx = block_max(mx, sh);
     tsum = block_sum(tsum, sh);
     double z = 0.0;
-    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) z += exp((double)g[i] - mx);
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) z += exp(base[i] + (double)f[i] - mx);
     z = block_sum(z, sh);
     const double logz = log(z);
     double l = 0.0;
     for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x) {
-        const double t = target_raw(p_hat[i], half_lambda, eps) / tsum;
-        const double lp = (double)g[i] - mx - logz;
+        const double t = target_raw(signal[i], base[i], beta, gamma, eps) / tsum;
+        const double lp = base[i] + (double)f[i] - mx - logz;
         l += t * (log(t) - lp);
         dg[i] = (float)((exp(lp) - t) / (double)nseg);
     }
@@ -400,12 +408,12 @@ int launch_pool_size(const int32_t *pool_idx, int64_t nnz, int32_t *size, hipStr
 }
 
 int launch_features(const int32_t *row_ptr, const int32_t *pool_idx, const uint8_t *y, const int32_t *size,
-                    int32_t n, double a_pos, double a_neg, float fp10, float fn10, double *score, float *X,
-                    hipStream_t s)
+                    int32_t n, double a_pos, double a_neg, double log100n, float fp10, float fn10, double *base,
+                    float *X, hipStream_t s)
 {
     hipLaunchKernelGGL(features_raw_kernel, dim3(grid_for(n, 256, 1 << 20)), dim3(256), 0, s, row_ptr, pool_idx,
-                       y, size, n, a_pos, a_neg, fp10, fn10, score, X);
-    hipLaunchKernelGGL(features_norm_kernel, dim3(1), dim3(256), 0, s, score, n, X);
+                       y, size, n, a_pos, a_neg, fp10, fn10, base, X);
+    hipLaunchKernelGGL(features_norm_kernel, dim3(1), dim3(256), 0, s, base, n, log100n, X);
     return (int)hipGetLastError();
 }
 
@@ -415,11 +423,11 @@ int launch_forward(const uint16_t *wb, const float *X, int64_t rows, float *g, i
     return (int)hipGetLastError();
 }
 
-int launch_loss(const float *g, const double *p_hat, const int64_t *seg_ptr, int32_t nseg, double lambda,
-                double eps, double *seg_loss, float *dg, hipStream_t s)
+int launch_loss(const float *f, const double *base, const double *signal, const int64_t *seg_ptr, int32_t nseg,
+                double beta, double gamma, double eps, double *seg_loss, float *df, hipStream_t s)
 {
-    hipLaunchKernelGGL(loss_kernel, dim3(nseg), dim3(256), 0, s, g, p_hat, seg_ptr, nseg, lambda / 2.0, eps,
-                       seg_loss, dg);
+    hipLaunchKernelGGL(loss_kernel, dim3(nseg), dim3(256), 0, s, f, base, signal, seg_ptr, nseg, beta, gamma, eps,
+                       seg_loss, df);
     return (int)hipGetLastError();
 }
 

@@ -61,21 +61,19 @@ int ensure_device_csr(mcpd_instance *I)
     return MCPD_OK;
 }
 
-// Features of an instance into device rows X (n * 8 floats), on stream s.
-int device_features(mcpd_instance *I, float *X, hipStream_t s)
+// Features of an instance into device rows X (n * 8 floats) and its base
+// logits into device base (n doubles), on stream s.
+int device_features(mcpd_instance *I, float *X, double *base, hipStream_t s)
 {
     int rc = ensure_device_csr(I);
     if (rc) return rc;
-    double *score = nullptr;
-    if ((rc = dev_alloc(&score, (size_t)I->n))) return rc;
     const double a_pos = std::log(1.0 - I->fn) - std::log(I->fp);
     const double a_neg = std::log(I->fn) - std::log(1.0 - I->fp);
-    int e = K::launch_features(I->d_row_ptr, I->d_pool_idx, I->d_y, I->d_pool_size, I->n, a_pos, a_neg,
-                               (float)(10.0 * I->fp), (float)(10.0 * I->fn), score, X, s);
-    hipError_t se = hipStreamSynchronize(s);
-    dev_free(score);
+    const double log100n = std::log(100.0 * (double)I->n);
+    int e = K::launch_features(I->d_row_ptr, I->d_pool_idx, I->d_y, I->d_pool_size, I->n, a_pos, a_neg, log100n,
+                               (float)(10.0 * I->fp), (float)(10.0 * I->fn), base, X, s);
     if (e != hipSuccess) return hip_fail((hipError_t)e, "feature kernels");
-    if (se != hipSuccess) return hip_fail(se, "hipStreamSynchronize");
+    HIP_TRY(hipStreamSynchronize(s));
     return MCPD_OK;
 }
 
@@ -96,11 +94,11 @@ struct mcpd_mlp {
     int64_t step = 0;
     // training set
     float *d_X = nullptr;
-    double *d_phat = nullptr;
+    double *d_base = nullptr, *d_signal = nullptr;
     int64_t *d_seg = nullptr;
     int32_t nseg = 0;
     int64_t rows = 0;
-    double lambda = 1.0, eps = 1e-3;
+    double beta = 1.0, gamma = 0.0, eps = 1e-3;
     float *d_g = nullptr, *d_dg = nullptr, *d_part = nullptr;
     double *d_seg_loss = nullptr, *d_loss = nullptr;
     int nblocks = 0;
@@ -108,7 +106,7 @@ struct mcpd_mlp {
 
     void drop_data()
     {
-        dev_free(d_X); dev_free(d_phat); dev_free(d_seg); dev_free(d_g); dev_free(d_dg);
+        dev_free(d_X); dev_free(d_base); dev_free(d_signal); dev_free(d_seg); dev_free(d_g); dev_free(d_dg);
         dev_free(d_part); dev_free(d_seg_loss); dev_free(d_loss);
         rows = 0;
         nseg = 0;
@@ -140,7 +138,8 @@ int alloc_data(mcpd_mlp *M, int64_t rows, int32_t nseg)
 {
     M->drop_data();
     int rc;
-    if ((rc = dev_alloc(&M->d_X, (size_t)rows * MCPD_MLP_FEATURES)) || (rc = dev_alloc(&M->d_phat, (size_t)rows)) ||
+    if ((rc = dev_alloc(&M->d_X, (size_t)rows * MCPD_MLP_FEATURES)) || (rc = dev_alloc(&M->d_signal, (size_t)rows)) ||
+        (rc = dev_alloc(&M->d_base, (size_t)rows)) ||
         (rc = dev_alloc(&M->d_seg, (size_t)nseg + 1)) || (rc = dev_alloc(&M->d_g, (size_t)rows)) ||
         (rc = dev_alloc(&M->d_dg, (size_t)rows)) || (rc = dev_alloc(&M->d_seg_loss, (size_t)nseg)) ||
         (rc = dev_alloc(&M->d_loss, (size_t)1)))
@@ -152,9 +151,10 @@ int alloc_data(mcpd_mlp *M, int64_t rows, int32_t nseg)
     return MCPD_OK;
 }
 
-int check_hp(double lambda, double eps)
+int check_hp(double beta, double gamma, double eps)
 {
-    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(MCPD_EINVAL, "lambda must be >= 0");
+    if (!(beta >= 0.0 && gamma >= 0.0) || !std::isfinite(beta) || !std::isfinite(gamma))
+        return fail(MCPD_EINVAL, "target exponents must be finite and >= 0");
     if (!(eps > 0.0) || !std::isfinite(eps)) return fail(MCPD_EINVAL, "eps must be > 0");
     return MCPD_OK;
 }
@@ -165,8 +165,8 @@ int loss_grad_device(mcpd_mlp *M, double *loss_dst)
 {
     int e = K::launch_forward(M->d_wb, M->d_X, M->rows, M->d_g, M->cus, M->stream);
     if (e == hipSuccess)
-        e = K::launch_loss(M->d_g, M->d_phat, M->d_seg, M->nseg, M->lambda, M->eps, M->d_seg_loss, M->d_dg,
-                           M->stream);
+        e = K::launch_loss(M->d_g, M->d_base, M->d_signal, M->d_seg, M->nseg, M->beta, M->gamma, M->eps,
+                           M->d_seg_loss, M->d_dg, M->stream);
     if (e == hipSuccess) e = K::launch_sum(M->d_seg_loss, M->nseg, 1.0 / M->nseg, loss_dst, M->stream);
     if (e == hipSuccess)
         e = K::launch_backward(M->d_wb, M->d_X, M->d_dg, M->rows, M->nblocks, M->rows_per_block, M->d_part,
@@ -179,18 +179,21 @@ int loss_grad_device(mcpd_mlp *M, double *loss_dst)
 
 extern "C" {
 
-int mcpd_features(mcpd_instance *I, float *out)
+int mcpd_features(mcpd_instance *I, float *out, double *base_out)
 {
     if (!I || !out) return fail(MCPD_EINVAL, "null argument");
     float *X = nullptr;
+    double *base = nullptr;
     int rc = dev_alloc(&X, (size_t)I->n * MCPD_MLP_FEATURES);
-    if (rc) return rc;
-    rc = device_features(I, X, I->stream);
+    if (!rc) rc = dev_alloc(&base, (size_t)I->n);
+    if (!rc) rc = device_features(I, X, base, I->stream);
     if (!rc) {
         hipError_t e = hipMemcpy(out, X, (size_t)I->n * MCPD_MLP_FEATURES * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && base_out) e = hipMemcpy(base_out, base, (size_t)I->n * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) rc = hip_fail(e, "hipMemcpy");
     }
     dev_free(X);
+    dev_free(base);
     return rc;
 }
 
@@ -249,47 +252,52 @@ int mcpd_mlp_forward(mcpd_mlp *M, const float *x, int64_t rows, float *g)
     return rc;
 }
 
-int mcpd_mlp_set_training_rows(mcpd_mlp *M, const float *x, const double *p_hat, int64_t rows,
-                               const int64_t *seg_ptr, int32_t nseg, double lambda, double eps)
+int mcpd_mlp_set_training_rows(mcpd_mlp *M, const float *x, const double *base, const double *signal, int64_t rows,
+                               const int64_t *seg_ptr, int32_t nseg, double beta, double gamma, double eps)
 {
-    if (!M || !x || !p_hat || !seg_ptr || rows <= 0 || nseg <= 0) return fail(MCPD_EINVAL, "bad argument");
-    int rc = check_hp(lambda, eps);
+    if (!M || !x || !base || !signal || !seg_ptr || rows <= 0 || nseg <= 0) return fail(MCPD_EINVAL, "bad argument");
+    int rc = check_hp(beta, gamma, eps);
     if (rc) return rc;
     if (seg_ptr[0] != 0 || seg_ptr[nseg] != rows) return fail(MCPD_EINVAL, "segments must cover the rows");
     for (int32_t s = 0; s < nseg; ++s)
         if (seg_ptr[s + 1] <= seg_ptr[s]) return fail(MCPD_EINVAL, "empty or decreasing segment");
     for (int64_t r = 0; r < rows; ++r)
-        if (!std::isfinite(p_hat[r])) return fail(MCPD_EINVAL, "p_hat must be finite");
+        if (!std::isfinite(signal[r]) || !std::isfinite(base[r]) || base[r] > 0.0)
+            return fail(MCPD_EINVAL, "signal must be finite and base finite and <= 0");
     if ((rc = alloc_data(M, rows, nseg))) return rc;
-    M->lambda = lambda;
+    M->beta = beta;
+    M->gamma = gamma;
     M->eps = eps;
     HIP_TRY(hipMemcpyAsync(M->d_X, x, (size_t)rows * MCPD_MLP_FEATURES * 4, hipMemcpyHostToDevice, M->stream));
-    HIP_TRY(hipMemcpyAsync(M->d_phat, p_hat, (size_t)rows * 8, hipMemcpyHostToDevice, M->stream));
+    HIP_TRY(hipMemcpyAsync(M->d_signal, signal, (size_t)rows * 8, hipMemcpyHostToDevice, M->stream));
+    HIP_TRY(hipMemcpyAsync(M->d_base, base, (size_t)rows * 8, hipMemcpyHostToDevice, M->stream));
     HIP_TRY(hipMemcpyAsync(M->d_seg, seg_ptr, ((size_t)nseg + 1) * 8, hipMemcpyHostToDevice, M->stream));
     HIP_TRY(hipStreamSynchronize(M->stream));
     return MCPD_OK;
 }
 
-int mcpd_mlp_set_training_data(mcpd_mlp *M, mcpd_instance *const *insts, const double *const *p_hat,
-                               int32_t count, double lambda, double eps)
+int mcpd_mlp_set_training_data(mcpd_mlp *M, mcpd_instance *const *insts, const double *const *signal,
+                               int32_t count, double beta, double gamma, double eps)
 {
-    if (!M || !insts || !p_hat || count <= 0) return fail(MCPD_EINVAL, "bad argument");
-    int rc = check_hp(lambda, eps);
+    if (!M || !insts || !signal || count <= 0) return fail(MCPD_EINVAL, "bad argument");
+    int rc = check_hp(beta, gamma, eps);
     if (rc) return rc;
     std::vector<int64_t> seg((size_t)count + 1, 0);
     for (int32_t i = 0; i < count; ++i) {
-        if (!insts[i] || !p_hat[i]) return fail(MCPD_EINVAL, "null instance or p_hat");
+        if (!insts[i] || !signal[i]) return fail(MCPD_EINVAL, "null instance or signal");
         seg[i + 1] = seg[i] + insts[i]->n;
         for (int32_t j = 0; j < insts[i]->n; ++j)
-            if (!std::isfinite(p_hat[i][j])) return fail(MCPD_EINVAL, "p_hat must be finite");
+            if (!std::isfinite(signal[i][j])) return fail(MCPD_EINVAL, "signal must be finite");
     }
     const int64_t rows = seg[count];
     if ((rc = alloc_data(M, rows, count))) return rc;
-    M->lambda = lambda;
+    M->beta = beta;
+    M->gamma = gamma;
     M->eps = eps;
     for (int32_t i = 0; i < count; ++i) {
-        if ((rc = device_features(insts[i], M->d_X + seg[i] * MCPD_MLP_FEATURES, M->stream))) return rc;
-        HIP_TRY(hipMemcpyAsync(M->d_phat + seg[i], p_hat[i], (size_t)insts[i]->n * 8, hipMemcpyHostToDevice,
+        if ((rc = device_features(insts[i], M->d_X + seg[i] * MCPD_MLP_FEATURES, M->d_base + seg[i], M->stream)))
+            return rc;
+        HIP_TRY(hipMemcpyAsync(M->d_signal + seg[i], signal[i], (size_t)insts[i]->n * 8, hipMemcpyHostToDevice,
                                M->stream));
     }
     HIP_TRY(hipMemcpyAsync(M->d_seg, seg.data(), seg.size() * 8, hipMemcpyHostToDevice, M->stream));
@@ -345,30 +353,36 @@ int mcpd_set_learned_weights(mcpd_instance *I, mcpd_mlp *M, double alpha, double
     if (!I || !M) return fail(MCPD_EINVAL, "null argument");
     if (!(alpha > 0.0 && alpha <= 1.0)) return fail(MCPD_EINVAL, "alpha must be in (0, 1]");
     const size_t n = (size_t)I->n;
-    float *X = nullptr, *dg = nullptr;
+    float *X = nullptr, *df = nullptr;
+    double *dbase = nullptr;
     int rc = dev_alloc(&X, n * MCPD_MLP_FEATURES);
-    if (!rc) rc = dev_alloc(&dg, n);
-    std::vector<float> g(n);
-    if (!rc) rc = device_features(I, X, M->stream);
+    if (!rc) rc = dev_alloc(&df, n);
+    if (!rc) rc = dev_alloc(&dbase, n);
+    std::vector<float> f(n);
+    std::vector<double> c(n);
+    if (!rc) rc = device_features(I, X, dbase, M->stream);
     if (!rc) {
-        hipError_t e = (hipError_t)K::launch_forward(M->d_wb, X, (int64_t)n, dg, M->cus, M->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(g.data(), dg, n * 4, hipMemcpyDeviceToHost, M->stream);
+        hipError_t e = (hipError_t)K::launch_forward(M->d_wb, X, (int64_t)n, df, M->cus, M->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(f.data(), df, n * 4, hipMemcpyDeviceToHost, M->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(c.data(), dbase, n * 8, hipMemcpyDeviceToHost, M->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(M->stream);
         if (e != hipSuccess) rc = hip_fail(e, "forward");
     }
     dev_free(X);
-    dev_free(dg);
+    dev_free(df);
+    dev_free(dbase);
     if (rc) return rc;
-    // w = (1 - alpha) softmax(g) + alpha / n, in FP64
+    // w = (1 - alpha) softmax(c + f) + alpha / n, in FP64
+    std::vector<double> w(n);
     double gmax = -INFINITY;
     for (size_t i = 0; i < n; ++i) {
-        if (!std::isfinite(g[i])) return fail(MCPD_EINVAL, "network output is not finite");
-        gmax = std::max(gmax, (double)g[i]);
+        w[i] = c[i] + (double)f[i];
+        if (!std::isfinite(w[i])) return fail(MCPD_EINVAL, "network output is not finite");
+        gmax = std::max(gmax, w[i]);
     }
-    std::vector<double> w(n);
     double z = 0.0;
     for (size_t i = 0; i < n; ++i) {
-        w[i] = std::exp((double)g[i] - gmax);
+        w[i] = std::exp(w[i] - gmax);
         z += w[i];
     }
     for (size_t i = 0; i < n; ++i) w[i] = (1.0 - alpha) * (w[i] / z) + alpha / (double)n;

@@ -231,3 +231,20 @@ def mlp_init(seed: int = 0) -> np.ndarray:
         b = 1.0 / np.sqrt(fan_in)
         parts.append(rng.uniform(-b, b, count))
     return np.concatenate(parts).astype(np.float32)
+
+
+def heldout_large(seed: int, n: int = 20000, budget: int = 1 << 28) -> (Instance, RunParams):
+    """A fresh large instance drawn like the uneven batch (m = 7.5% of n,
+    degree ~ U{3..7}, positives ~ U{1..10}, fp, fn ~ U[0.01, 0.20], q =
+    positives / n), run at the given budget (2^28 by default) with B about
+    four sweeps."""
+    rng = np.random.default_rng(seed)
+    m = int(round(0.075 * n))
+    npos = int(rng.integers(1, 11))
+    fp = float(rng.uniform(0.01, 0.20))
+    fn = float(rng.uniform(0.01, 0.20))
+    inst = make_instance(f"heldout{seed}_n{n}", n, m, (3, 7), npos, fp, fn, prior=npos / n,
+                         seed=int(rng.integers(1 << 31)))
+    slots = 64 * -(-budget // (4 * n * 64))
+    k, l = window_for_sweeps(1, n)
+    return inst, RunParams(budget=budget, slots=slots, k=k, m=l, seed=0)

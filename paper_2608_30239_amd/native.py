@@ -130,13 +130,14 @@ def load(path: Optional[str] = None):
         L.mcpd_batch_destroy.restype = None
         L.mcpd_run_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_uint64, C.POINTER(RunOpts), vp, vp,
                                      vp, vp]
-        L.mcpd_features.argtypes = [vp, vp]
+        L.mcpd_features.argtypes = [vp, vp, vp]
         L.mcpd_mlp_create.argtypes = [vp, vp, C.POINTER(vp)]
         L.mcpd_mlp_get_params.argtypes = [vp, vp, vp]
         L.mcpd_mlp_set_params.argtypes = [vp, vp]
         L.mcpd_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
-        L.mcpd_mlp_set_training_rows.argtypes = [vp, vp, vp, C.c_int64, vp, C.c_int32, C.c_double, C.c_double]
-        L.mcpd_mlp_set_training_data.argtypes = [vp, vp, vp, C.c_int32, C.c_double, C.c_double]
+        L.mcpd_mlp_set_training_rows.argtypes = [vp, vp, vp, vp, C.c_int64, vp, C.c_int32, C.c_double,
+                                                 C.c_double, C.c_double]
+        L.mcpd_mlp_set_training_data.argtypes = [vp, vp, vp, C.c_int32, C.c_double, C.c_double, C.c_double]
         L.mcpd_mlp_loss_grad.argtypes = [vp, vp, vp]
         L.mcpd_mlp_train.argtypes = [vp, C.c_int32, C.POINTER(AdamW), vp]
         L.mcpd_set_learned_weights.argtypes = [vp, vp, C.c_double, vp]
@@ -323,9 +324,11 @@ class Batch:
 
 
 def mcpd_features(dec):
+    """(features [n, 8] float32, base logits [n] float64)."""
     X = np.zeros((dec.n, MLP_FEATURES), np.float32)
-    _check(load().mcpd_features(dec.h, _p(X)), "mcpd_features")
-    return X
+    c = np.zeros(dec.n)
+    _check(load().mcpd_features(dec.h, _p(X), _p(c)), "mcpd_features")
+    return X, c
 
 
 class Mlp:
@@ -357,17 +360,18 @@ class Mlp:
         _check(load().mcpd_mlp_forward(self.h, _p(X), X.shape[0], _p(g)), "mcpd_mlp_forward")
         return g
 
-    def set_training_rows(self, X, p_hat, seg_ptr, lam=1.0, eps=1e-3):
+    def set_training_rows(self, X, base, signal, seg_ptr, beta=1.0, gamma=0.0, eps=1e-3):
         X = np.ascontiguousarray(X, np.float32)
-        p_hat = np.ascontiguousarray(p_hat, np.float64)
+        base = np.ascontiguousarray(base, np.float64)
+        signal = np.ascontiguousarray(signal, np.float64)
         seg = np.ascontiguousarray(seg_ptr, np.int64)
-        _check(load().mcpd_mlp_set_training_rows(self.h, _p(X), _p(p_hat), X.shape[0], _p(seg), len(seg) - 1,
-                                                 lam, eps), "mcpd_mlp_set_training_rows")
+        _check(load().mcpd_mlp_set_training_rows(self.h, _p(X), _p(base), _p(signal), X.shape[0], _p(seg),
+                                                 len(seg) - 1, beta, gamma, eps), "mcpd_mlp_set_training_rows")
 
-    def set_training_data(self, decoders, p_hats, lam=1.0, eps=1e-3):
-        ph = [np.ascontiguousarray(p, np.float64) for p in p_hats]
+    def set_training_data(self, decoders, signals, beta=1.0, gamma=0.0, eps=1e-3):
+        ph = [np.ascontiguousarray(p, np.float64) for p in signals]
         insts = (C.c_void_p * len(decoders))(*[d.h.value for d in decoders])
-        _check(load().mcpd_mlp_set_training_data(self.h, insts, _ptr_array(ph), len(decoders), lam, eps),
+        _check(load().mcpd_mlp_set_training_data(self.h, insts, _ptr_array(ph), len(decoders), beta, gamma, eps),
                "mcpd_mlp_set_training_data")
 
     def loss_grad(self):

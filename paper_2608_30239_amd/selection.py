@@ -1,0 +1,255 @@
+"""Learned selection weights: training on the method's own outputs and the
+equal-budget comparison with the paper's score weights.
+
+Everything numerical runs in the library's kernels (sampler, features,
+network, loss, AdamW); this module only sequences calls and keeps score.
+
+Training signal.  With random-scan weights w, the variance of clone j's
+estimate behaves like sigma_j^2 / w_j per unit of budget, and the method's
+own standard errors give sigma_j ~ SE_j sqrt(w_j).  The allocation that
+minimises sum_j sigma_j^2 / w_j is w ~ sigma.  The network learns, from
+per-clone features only, a move of the score softmax towards it: the target
+of an instance is t ~ exp((1 - rho) c) (v + eps)^rho with c the score
+log-weights and v = sigma / max sigma measured on the uneven batch.
+
+Comparison at equal budget (the weights change neither the budget nor the
+slots): for each instance, a reference is the mean of `nref` independent
+runs with the score weights (seeds 1000...); each weighting is then run
+`nrep` times (seeds 0...) and scored by
+    MSE = mean over runs of mean_j (theta_hat_j - ref_j)^2 - mean_j Var(ref_j)
+(the reference's own variance removed) and by the mean device time per run;
+efficiency = 1 / (MSE * seconds), and the gain of a weighting is its
+efficiency over the score weights' efficiency.
+
+The estimator is unbiased (Theorem 2), so its MSE is its variance, which
+each run also estimates from its own slots: VAR = mean over runs of
+mean_j SE_j^2.  That estimate pools every slot of every run instead of
+`nrep` run-level errors, so it is far less noisy under the heavy tails of
+the per-slot estimates; `var_efficiency` = 1 / (VAR * seconds) is what the
+choice of the training target uses.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict
+
+import numpy as np
+
+from . import instances as I
+from . import native as N
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+TRAINED = os.path.join(PKG, "selection_mlp.npz")
+
+
+def initial_params(seed=0):
+    """The uniform initialisation with the output layer zeroed, so that
+    training starts from the score weights (f = 0)."""
+    theta = I.mlp_init(seed)
+    theta[-(N.MLP_HIDDEN + 1):] = 0.0
+    return theta
+
+
+def uneven_outputs(seed: int = 4, runs: int = 4):
+    """Decoders of the uneven batch (256 instances, 2^24 updates each) and,
+    per instance, the training signal v = sigma / max sigma from `runs`
+    batched launches with the score weights."""
+    insts, params = I.uneven_batch(seed=seed)
+    decs = [N.Decoder(x) for x in insts]
+    bt = N.Batch(decs, [(p.budget, p.slots, p.k, p.m) for p in params])
+    try:
+        res = [bt.run(r) for r in range(runs)]
+    finally:
+        bt.close()
+    signals = []
+    for i, d in enumerate(decs):
+        se2 = np.mean([r[i]["stderr"] ** 2 for r in res], axis=0)
+        w, _ = d.weights()
+        sig = np.sqrt(se2 * w)
+        signals.append(sig / sig.max() if sig.max() > 0 else np.zeros_like(sig))
+    return decs, signals, res
+
+
+def train(decs, signals, rho, eps, steps=600, lr=3e-3, weight_decay=1e-4, init_seed=0):
+    net = N.Mlp(initial_params(init_seed))
+    net.set_training_data(decs, signals, 1.0 - rho, rho, eps)
+    t0 = time.perf_counter()
+    hist = net.train(steps, lr=lr, weight_decay=weight_decay)
+    return net, hist, time.perf_counter() - t0
+
+
+class Comparison:
+    """Equal-budget runs of one instance under several weightings."""
+
+    def __init__(self, inst, rp, nref=64):
+        self.inst, self.rp = inst, rp
+        self.dec = N.Decoder(inst)
+        self.dec.set_weights(None)
+        runs = [self._run(1000 + s) for s in range(nref)]
+        M = np.array([r["marginals"] for r in runs])
+        self.ref = M.mean(axis=0)
+        self.ref_var = float((M.var(axis=0, ddof=1) / nref).mean())
+        self.results: Dict[str, dict] = {}
+
+    def _run(self, seed):
+        rp = self.rp
+        return self.dec.run(rp.budget, rp.slots, rp.k, rp.m, seed)
+
+    def measure(self, name, set_weights, nrep):
+        set_weights(self.dec)
+        errs, ms, var = [], [], []
+        for s in range(nrep):
+            r = self._run(s)
+            errs.append(float(np.mean((r["marginals"] - self.ref) ** 2)))
+            var.append(float(np.mean(r["stderr"] ** 2)))
+            ms.append(r["stats"]["kernel_ms"])
+        self.dec.set_weights(None)
+        mse = float(np.mean(errs)) - self.ref_var
+        v = float(np.mean(var))
+        sec = float(np.mean(ms)) / 1e3
+        out = dict(mse=mse, rmse=float(np.sqrt(max(mse, 0.0))), seconds=sec,
+                   efficiency=(1.0 / (mse * sec)) if mse > 0 else float("inf"),
+                   var=v, var_efficiency=1.0 / (v * sec), run_mse=errs, run_var=var, run_ms=ms)
+        self.results[name] = out
+        return out
+
+    def gain(self, name, base="score", key="efficiency"):
+        return self.results[name][key] / self.results[base][key]
+
+    def close(self):
+        self.dec.close()
+
+
+def score_weights(dec):
+    dec.set_weights(None)
+
+
+def learned_weights(net, alpha=0.5):
+    return lambda dec: net.apply(dec, alpha)
+
+
+def judge(dec, net, rp, frac=16, seed=1 << 20, alpha=0.5):
+    """The score weights as judge: a pilot on 1/frac of the slots at the same
+    horizon B with each weighting (slots are i.i.d., so the per-slot variance
+    is the same as in the full run), then the weighting with the larger
+    1 / (sum_j SE_j^2 * P_pilot * seconds) is kept.  Returns (choice, pilot
+    seconds)."""
+    P = max(64, rp.slots // frac)
+    budget = (rp.budget // rp.slots) * P
+    eff, sec = {}, 0.0
+    for name in ("score", "learned"):
+        if name == "score":
+            dec.set_weights(None)
+        else:
+            net.apply(dec, alpha)
+        r = dec.run(budget, P, rp.k, rp.m, seed)
+        s = r["stats"]["kernel_ms"] / 1e3
+        sec += s
+        eff[name] = 1.0 / (float(np.mean(r["stderr"] ** 2)) * P * s)
+    choice = "learned" if eff["learned"] > eff["score"] else "score"
+    if choice == "score":
+        dec.set_weights(None)
+    else:
+        net.apply(dec, alpha)
+    return choice, sec
+
+
+def validation_set():
+    """Held-out instances for choosing the target (not used for the final
+    comparison): n = 3000, 6000, 12000 drawn like the uneven batch, at
+    budget 2^26, and the paper-shaped design with new outcomes."""
+    out = [I.heldout_large(2000 + i, n=n, budget=1 << 26) for i, n in enumerate((3000, 6000, 12000))]
+    inst = I.make_instance("knill_val", 1298, 97, 5, 3, 0.05, 0.10, prior=3 / 1298, seed=77, design_seed=1)
+    k, l = I.window_for_sweeps(1, 1298)
+    out.append((inst, I.RunParams(budget=1 << 26, slots=16384, k=k, m=l, seed=0)))
+    return out
+
+
+def evaluation_set():
+    """The final comparison: the paper-shaped instance and four fresh
+    20000-clone instances, at budget 2^28."""
+    return [I.paper_shaped()] + [I.heldout_large(1000 + i) for i in range(4)]
+
+
+# (rho, eps) of the target t ~ exp((1 - rho) c) (v + eps)^rho
+CANDIDATES = ((0.1, 1e-3), (0.15, 1e-3), (0.2, 1e-3), (0.3, 1e-3), (0.15, 1e-2), (0.3, 1e-2))
+
+
+def main(out=TRAINED, steps=600, nrep=12, log=print):
+    t0 = time.perf_counter()
+    decs, signals, res = uneven_outputs()
+    log(f"uneven batch: {len(res)} runs of {sum(r['stats']['progress_units'] for r in res[0])} updates, "
+        f"{res[0][0]['stats']['kernel_ms']:.1f} ms each")
+    nets = {}
+    for rho, eps in CANDIDATES:
+        net, hist, sec = train(decs, signals, rho, eps, steps=steps)
+        nets[(rho, eps)] = net
+        log(f"target rho={rho} eps={eps}: loss {hist[0]:.4f} -> {hist[-1]:.4f} in {sec:.2f} s")
+    for d in decs:
+        d.close()
+    gains = {c: [] for c in CANDIDATES}
+    for inst, rp in validation_set():
+        cmp_ = Comparison(inst, rp, nref=16)
+        cmp_.measure("score", score_weights, nrep)
+        for c, net in nets.items():
+            cmp_.measure(str(c), learned_weights(net), nrep)
+            gains[c].append(cmp_.gain(str(c), key="var_efficiency"))
+        log(f"validation {inst.name}: " + ", ".join(f"{c}: {g[-1]:.2f}" for c, g in gains.items()))
+        cmp_.close()
+    geo = {c: float(np.exp(np.mean(np.log(np.maximum(g, 1e-12))))) for c, g in gains.items()}
+    best = max(geo, key=geo.get)
+    master, _ = nets[best].params()
+    report = dict(target=dict(rho=best[0], eps=best[1]), steps=steps,
+                  validation_var_gain_geomean={str(c): v for c, v in geo.items()},
+                  validation_var_gains={str(c): g for c, g in gains.items()},
+                  seconds=time.perf_counter() - t0)
+    np.savez(out, params=master, report=json.dumps(report))
+    for net in nets.values():
+        net.close()
+    log(json.dumps(report))
+    return report
+
+
+def evaluate(net, nref=64, nrep=24, instances=None, log=print):
+    """Learned against score weights on the evaluation set at equal budget:
+    per instance the reference-based MSE, the variance from the runs' own
+    standard errors, device seconds and both gains."""
+    rows = []
+    for inst, rp in (instances or evaluation_set()):
+        cmp_ = Comparison(inst, rp, nref=nref)
+        s = cmp_.measure("score", score_weights, nrep)
+        l = cmp_.measure("learned", learned_weights(net), nrep)
+        choice, pilot_sec = judge(cmp_.dec, net, rp)
+        j = cmp_.results[choice]
+        # the judged weighting pays for its pilot once per instance, spread
+        # over the runs it serves
+        judged_eff = 1.0 / (j["mse"] * (j["seconds"] + pilot_sec / nrep)) if j["mse"] > 0 else float("inf")
+        cmp_.dec.set_weights(None)
+        row = dict(instance=inst.name, n=inst.n, budget=rp.budget, slots=rp.slots,
+                   rmse_score=s["rmse"], rmse_learned=l["rmse"],
+                   var_score=s["var"], var_learned=l["var"],
+                   seconds_score=s["seconds"], seconds_learned=l["seconds"],
+                   gain=cmp_.gain("learned"), var_gain=cmp_.gain("learned", key="var_efficiency"),
+                   judge_choice=choice, judge_pilot_seconds=pilot_sec,
+                   judged_gain=judged_eff / s["efficiency"], ref_var=cmp_.ref_var)
+        rows.append(row)
+        log(json.dumps(row))
+        cmp_.close()
+    def geomean(key):
+        return float(np.exp(np.mean(np.log([max(r[key], 1e-12) for r in rows]))))
+    return dict(rows=rows, gain_geomean=geomean("gain"), var_gain_geomean=geomean("var_gain"),
+                judged_gain_geomean=geomean("judged_gain"))
+
+
+def load_trained(path=TRAINED):
+    """(FP32 master parameters, report dict) of the shipped network."""
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"].astype(np.float32), json.loads(str(z["report"]))
+
+
+if __name__ == "__main__":
+    import sys
+    main(out=sys.argv[1] if len(sys.argv) > 1 else TRAINED, log=lambda m: print(m, flush=True))

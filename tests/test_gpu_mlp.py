@@ -45,11 +45,15 @@ def test_features_match_oracle(k):
     inst = some_instances()[k]
     dec = N.Decoder(inst)
     try:
-        X = N.mcpd_features(dec)
+        X, c = N.mcpd_features(dec)
     finally:
         dec.close()
     ref = MO.features(inst)
-    assert np.array_equal(X, ref.astype(np.float32))
+    # FP64 values rounded once to FP32 (the base logits may differ from the
+    # oracle's in the last bit of log(100 n))
+    np.testing.assert_allclose(c, MO.base_logits(inst), rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(X, ref.astype(np.float32), rtol=2.0 ** -23, atol=1e-12)
+    assert np.array_equal(X[:, [0, 1, 2, 3, 4, 6, 7]], ref[:, [0, 1, 2, 3, 4, 6, 7]].astype(np.float32))
 
 
 def test_forward_and_bf16_copy():
@@ -77,25 +81,26 @@ def _training_rows(seed=3, sizes=(1, 255, 256, 257, 3000)):
     rng = np.random.default_rng(seed)
     rows = sum(sizes)
     X = rng.uniform(0, 1.5, (rows, 8)).astype(np.float32)
-    p_hat = rng.uniform(-0.05, 1.05, rows)
+    signal = rng.uniform(-0.05, 1.05, rows)
+    base = -rng.uniform(0, 12, rows)
     seg = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    return X, p_hat, seg
+    return X, base, signal, seg
 
 
-@pytest.mark.parametrize("lam,eps", [(1.0, 1e-3), (0.5, 1e-2), (2.0, 1e-4)])
-def test_loss_and_gradient_match_oracle(lam, eps):
+@pytest.mark.parametrize("beta,gamma,eps", [(1.0, 0.0, 1e-3), (0.75, 0.5, 1e-2), (0.0, 1.0, 1e-4)])
+def test_loss_and_gradient_match_oracle(beta, gamma, eps):
     theta = I.mlp_init(4)
-    X, p_hat, seg = _training_rows()
+    X, base, signal, seg = _training_rows()
     net = N.Mlp(theta)
     try:
-        net.set_training_rows(X, p_hat, seg, lam, eps)
+        net.set_training_rows(X, base, signal, seg, beta, gamma, eps)
         loss, grad = net.loss_grad()
     finally:
         net.close()
     tb = MO.bf16_round(theta).astype(np.float64)
     g, _ = MO.forward(tb, X.astype(np.float64))
-    t = MO.targets(p_hat, seg, lam, eps)
-    ref_loss, dg = MO.loss_and_dg(g, t, seg)
+    t = MO.targets(signal, base, seg, beta, gamma, eps)
+    ref_loss, dg = MO.loss_and_dg(g, base, t, seg)
     ref_grad = MO.backward(tb, X.astype(np.float64), dg)
     assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
     assert np.max(np.abs(grad - ref_grad)) <= 1e-4 * np.max(np.abs(ref_grad))
@@ -103,10 +108,10 @@ def test_loss_and_gradient_match_oracle(lam, eps):
 
 def test_single_row_segments_have_zero_loss():
     theta = I.mlp_init(5)
-    X, p_hat, _ = _training_rows(sizes=(1, 1, 1))
+    X, base, signal, _ = _training_rows(sizes=(1, 1, 1))
     net = N.Mlp(theta)
     try:
-        net.set_training_rows(X, p_hat, np.array([0, 1, 2, 3]))
+        net.set_training_rows(X, base, signal, np.array([0, 1, 2, 3]))
         loss, grad = net.loss_grad()
     finally:
         net.close()
@@ -115,11 +120,11 @@ def test_single_row_segments_have_zero_loss():
 
 def test_adamw_steps_match_oracle():
     theta = I.mlp_init(6)
-    X, p_hat, seg = _training_rows(seed=7)
+    X, base, signal, seg = _training_rows(seed=7)
     hp = dict(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-6, weight_decay=0.05)
     net = N.Mlp(theta)
     try:
-        net.set_training_rows(X, p_hat, seg)
+        net.set_training_rows(X, base, signal, seg, 0.75, 0.5, 1e-2)
         th = theta.astype(np.float64)
         m = np.zeros_like(th)
         v = np.zeros_like(th)
@@ -138,10 +143,10 @@ def test_adamw_steps_match_oracle():
 
 def test_training_lowers_the_loss():
     theta = I.mlp_init(8)
-    X, p_hat, seg = _training_rows(seed=9, sizes=(700, 900, 1300))
+    X, base, signal, seg = _training_rows(seed=9, sizes=(700, 900, 1300))
     net = N.Mlp(theta)
     try:
-        net.set_training_rows(X, p_hat, seg, 1.0, 1e-3)
+        net.set_training_rows(X, base, signal, seg, 0.5, 0.5, 1e-3)
         hist = net.train(150, lr=3e-3)
         loss, _ = net.loss_grad()
     finally:
@@ -156,14 +161,31 @@ def test_learned_weights_match_oracle_and_feed_the_sampler():
     net = N.Mlp(theta)
     dec = N.Decoder(inst)
     try:
-        X = N.mcpd_features(dec)
+        X, c = N.mcpd_features(dec)
         w = net.apply(dec, alpha=0.5)
         _, mass = dec.weights()
     finally:
         dec.close()
         net.close()
-    g, _ = MO.forward(MO.bf16_round(theta), X.astype(np.float64))
-    ref = MO.selection_weights(g, 0.5)
+    f, _ = MO.forward(MO.bf16_round(theta), X.astype(np.float64))
+    ref = MO.selection_weights(f, c, 0.5)
     assert np.max(np.abs(w - ref) / ref) <= 1e-5
     assert w.min() >= 0.5 / inst.n and abs(w.sum() - 1) < 1e-12
     assert np.array_equal(mass, O.quantize(w))
+
+
+@pytest.mark.parametrize("make", [I.tiny_plain, I.paper_shaped])
+def test_zero_network_gives_back_the_score_weights(make):
+    inst, _ = make()
+    net = N.Mlp(np.zeros(N.MLP_PARAMS, np.float32))
+    dec = N.Decoder(inst)
+    try:
+        _, score_mass = dec.weights()
+        w = net.apply(dec, alpha=0.5)
+        _, mass = dec.weights()
+    finally:
+        dec.close()
+        net.close()
+    _, ws = O.score_weights(inst)
+    assert np.array_equal(w, ws)
+    assert np.array_equal(mass, score_mass)

@@ -58,8 +58,20 @@ def test_features_by_hand():
     # score s_i = sum d_j a_j: a+ = log(0.9/0.05), a- = log(0.1/0.95)
     ap, an = np.log(0.9) - np.log(0.05), np.log(0.1) - np.log(0.95)
     s = np.array([2 * ap + 2 * an, 2 * an + 3 * ap, 3 * ap, 2 * ap + 3 * ap])
-    np.testing.assert_allclose(X[:, 5], (s - s.min()) / (s.max() - s.min()), rtol=0, atol=1e-15)
+    c = np.log(400.0) * (s - s.max()) / (s.max() - s.min())
+    np.testing.assert_allclose(M.base_logits(inst), c, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(X[:, 5], c / 16, rtol=0, atol=1e-14)
+    assert X[3, 5] == 0.0 and abs(X[0, 5] + np.log(400.0) / 16) < 1e-14   # top and bottom
     assert (X[:, 6] == 0.5).all() and (X[:, 7] == 1.0).all()
+
+
+def test_base_logits_give_the_score_weights():
+    inst, _ = I.tiny_plain()
+    _, w = __import__("oracle.oracle", fromlist=["x"]).score_weights(inst)
+    c = M.base_logits(inst)
+    # a network that outputs zero gives back the paper's weights
+    np.testing.assert_allclose(M.selection_weights(np.zeros(inst.n), c, 0.5), w, rtol=1e-13)
+    assert abs(c.max()) == 0.0 and abs(c.min() + np.log(100.0 * inst.n)) < 1e-12
 
 
 def test_features_equal_scores_give_zero():
@@ -94,51 +106,59 @@ def _random_problem(seed=2, rows=40, segs=(0, 13, 27, 40)):
     rng = np.random.default_rng(seed)
     theta = rng.uniform(-0.5, 0.5, M.N_PARAMS)
     X = rng.uniform(0, 1.5, (rows, 8))
-    p_hat = rng.uniform(-0.05, 1.05, rows)
+    signal = rng.uniform(-0.05, 1.05, rows)
+    base = -rng.uniform(0, 8, rows)
     seg = np.array(segs)
-    t = M.targets(p_hat, seg, lam=1.0, eps=1e-3)
-    return theta, X, t, seg
+    t = M.targets(signal, base, seg, 0.7, 0.5, 1e-3)
+    return theta, X, t, seg, base
 
 
-def test_targets_normalised_and_clipped():
-    theta, X, t, seg = _random_problem()
+def test_targets_normalised_and_special_cases():
+    theta, X, t, seg, base = _random_problem()
     for a, b in zip(seg[:-1], seg[1:]):
         assert abs(t[a:b].sum() - 1.0) < 1e-14
     assert (t > 0).all()
-    t0 = M.targets(np.array([0.3, 0.9, -0.2, 1.4]), np.array([0, 4]), lam=0.0, eps=0.5)
-    np.testing.assert_allclose(t0, 0.25)     # lambda = 0: uniform
-    t1 = M.targets(np.array([0.5, 0.0, -0.2]), np.array([0, 3]), lam=2.0, eps=0.0 + 1e-12)
-    np.testing.assert_allclose(t1, [1.0, 0.0, 0.0], atol=1e-10)   # clipped to 0
+    c = np.array([0.0, -1.0, -2.5, -4.0])
+    # beta = 1, gamma = 0: the score softmax itself
+    t1 = M.targets(np.array([0.3, 0.9, -0.2, 1.4]), c, np.array([0, 4]), 1.0, 0.0, 0.5)
+    np.testing.assert_allclose(t1, np.exp(c) / np.exp(c).sum(), rtol=1e-15)
+    # beta = 0, gamma = 1: proportional to clip(signal) + eps
+    t2 = M.targets(np.array([0.25, 1.0, 1.3, -0.5]), c, np.array([0, 4]), 0.0, 1.0, 0.25)
+    np.testing.assert_allclose(t2, np.array([0.5, 1.25, 1.25, 0.25]) / 3.25, rtol=1e-15)
+    # beta = gamma = 0: uniform
+    np.testing.assert_allclose(M.targets(np.zeros(4), c, np.array([0, 4]), 0.0, 0.0, 1.0), 0.25)
 
 
 def test_loss_zero_at_target_and_gradient():
     rng = np.random.default_rng(3)
-    g = rng.standard_normal(10)
+    f = rng.standard_normal(10)
+    base = -rng.uniform(0, 5, 10)
+    g = base + f
     seg = np.array([0, 4, 10])
     t = np.concatenate([np.exp(g[:4]) / np.exp(g[:4]).sum(), np.exp(g[4:]) / np.exp(g[4:]).sum()])
-    loss, dg = M.loss_and_dg(g, t, seg)
+    loss, dg = M.loss_and_dg(f, base, t, seg)
     assert abs(loss) < 1e-15 and np.max(np.abs(dg)) < 1e-15
-    t2 = M.targets(rng.uniform(0, 1, 10), seg, 1.0, 1e-3)
-    loss, dg = M.loss_and_dg(g, t2, seg)
+    t2 = M.targets(rng.uniform(0, 1, 10), base, seg, 0.5, 0.5, 1e-3)
+    loss, dg = M.loss_and_dg(f, base, t2, seg)
     assert loss > 0
     h = 1e-6
     for i in range(10):
         e = np.zeros(10); e[i] = h
-        fd = (M.loss_and_dg(g + e, t2, seg)[0] - M.loss_and_dg(g - e, t2, seg)[0]) / (2 * h)
+        fd = (M.loss_and_dg(f + e, base, t2, seg)[0] - M.loss_and_dg(f - e, base, t2, seg)[0]) / (2 * h)
         assert abs(fd - dg[i]) < 1e-8
 
 
 def test_backward_matches_finite_differences():
-    theta, X, t, seg = _random_problem()
+    theta, X, t, seg, base = _random_problem()
 
     def loss_of(th):
         g, _ = M.forward(th, X)
-        return M.loss_and_dg(g, t, seg)[0]
+        return M.loss_and_dg(g, base, t, seg)[0]
 
     g, c = M.forward(theta, X)
     # keep away from ReLU kinks so that central differences are valid
     assert min(np.min(np.abs(c["z1"])), np.min(np.abs(c["z2"]))) > 1e-4
-    _, dg = M.loss_and_dg(g, t, seg)
+    _, dg = M.loss_and_dg(g, base, t, seg)
     grad = M.backward(theta, X, dg)
     rng = np.random.default_rng(4)
     idx = np.concatenate([rng.choice(512, 20, replace=False),            # W1
@@ -172,6 +192,8 @@ def test_adamw_first_steps_closed_form():
 def test_selection_weights_floor_and_sum():
     rng = np.random.default_rng(5)
     g = rng.standard_normal(100) * 5
-    w = M.selection_weights(g, 0.5)
+    w = M.selection_weights(g, np.zeros(100), 0.5)
     assert abs(w.sum() - 1) < 1e-14 and (w >= 0.5 / 100).all()
-    np.testing.assert_allclose(M.selection_weights(np.full(7, 3.0)), 1 / 7, rtol=1e-15)
+    np.testing.assert_allclose(M.selection_weights(np.full(7, 3.0), np.zeros(7)), 1 / 7, rtol=1e-15)
+    # only c + f matters
+    np.testing.assert_allclose(M.selection_weights(g - 1.5, np.full(100, 1.5)), w, rtol=1e-14)
