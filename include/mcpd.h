@@ -76,8 +76,19 @@ typedef struct mcpd_run_opts {
                                (default), 0 = plain stream launches           */
     uint32_t keep_slot_records; /* batches: keep N*_p and S_p of every slot on
                                the device for mcpd_batch_slot_records         */
+    uint32_t narrow_lanes;  /* least lanes of a narrow LDS layout, in which a
+                               workgroup runs only as many slots as fit their
+                               chain state in LDS: 0 = default (8), 256 = wide
+                               layouts only (state in LDS for 256 lanes or in
+                               global memory)                                 */
     uint32_t bucket_rows;   /* rows provided in bucket_sum / bucket_sumsq; must
                                be >= the largest N*                            */
+    uint32_t kernel;        /* 0 = auto: the cooperative kernel when every
+                               instance's chain states fit it, else the lane
+                               kernel; 1 = lane kernel (one slot per lane);
+                               2 = cooperative kernel (one slot per wavefront,
+                               64 speculative draws per step), MCPD_EINVAL if
+                               the states do not fit                          */
     /* Optional host outputs of mcpd_run_unbiased (NULL = not wanted; must be
        NULL for batches). */
     uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */
@@ -107,8 +118,13 @@ typedef struct mcpd_run_stats {
     uint64_t list_overflows;      /* slots whose touched-clone list overflowed
                                      (their numerators were flushed by a scan)  */
     uint64_t lanes;               /* persistent lanes of the launch             */
-    uint32_t placement;           /* bit 0: chain state in LDS; bit 1: tables in LDS */
+    uint32_t placement;           /* bit 0: chain state in LDS; bit 1: tables in
+                                     LDS; bit 2: cooperative kernel             */
     uint32_t wg_per_cu;           /* workgroups per CU of the launch            */
+    uint32_t wg_slots;            /* slots a workgroup runs at once for this
+                                     instance: 256 lanes (fewer in a narrow
+                                     layout) or 4 wavefronts (cooperative)     */
+    uint32_t kernel;              /* 1 = lane kernel, 2 = cooperative kernel    */
     double kernel_ms;             /* device time: the sampler launch, or for a
                                      batch replayed as a graph the whole replay
                                      (key copy, zeroing, sampler, copy back)   */
@@ -118,6 +134,9 @@ typedef struct mcpd_run_stats {
 typedef struct mcpd_tune_entry {
     uint32_t wg_per_cu;
     uint32_t ticket_slots;
+    uint32_t narrow_lanes;        /* least lanes of a narrow LDS layout (0 = wide
+                                     layouts only)                              */
+    uint32_t kernel;              /* 1 = lane kernel, 2 = cooperative kernel    */
     double ms;                    /* sampler time of one full run               */
 } mcpd_tune_entry;
 
@@ -197,8 +216,9 @@ void mcpd_destroy(mcpd_instance *inst);
  *            mcpd_run_unbiased gives with instance_id = opts->instance_id + i
  *   hip_stream  stream of the batch's device work (NULL = a stream the batch
  *            creates; graphs cannot be captured on the legacy default stream)
- * Creation plans the launch: the row format, each instance's placement in
- * LDS, the work tickets (longest slots first) and the workspace; the first
+ * Creation plans the launch: the kernel, the row format, each instance's
+ * placement in LDS, the work tickets (longest slots first) and the
+ * workspace; the first
  * run captures the device work of a run in a HIP graph (use_graph = 1) that
  * later runs replay.  Errors: MCPD_EINVAL, MCPD_ENOMEM, MCPD_EDEVICE. */
 int mcpd_batch_create(mcpd_instance *const *insts, int32_t count, const uint64_t *budget,
@@ -212,16 +232,21 @@ int mcpd_batch_create(mcpd_instance *const *insts, int32_t count, const uint64_t
 int mcpd_batch_run(mcpd_batch *batch, uint64_t seed, double *const *marginals,
                    double *const *stderr_out, uint64_t *const *hist, mcpd_run_stats *stats);
 
-/* Autotuner: run the batch once per candidate launch shape (workgroups per
- * CU x slots per ticket, within opts' fixed values), time the sampler, keep
- * the fastest.  The results do not depend on the shape.  entries: host [cap]
- * or NULL; count receives the number of candidates measured. */
+/* Autotuner: run the batch once per candidate launch shape (kernel x
+ * workgroups per CU x slots per ticket x LDS layout, within opts' fixed
+ * values), time the sampler, keep the fastest.  Lane kernel layouts: wide
+ * only (chain state in LDS for 256 lanes when it fits, else in global
+ * memory), or also narrow (a workgroup runs only as many lanes as fit the
+ * state in LDS, at least 8); cooperative kernel: one state per wavefront.
+ * The results do not depend on the shape.  entries: host [cap] or NULL;
+ * count receives the number of candidates measured. */
 int mcpd_batch_tune(mcpd_batch *batch, uint64_t seed, mcpd_tune_entry *entries, uint32_t cap,
                     uint32_t *count);
 
-/* The batch's current launch shape; placement: host [count] or NULL. */
+/* The batch's current launch shape; placement and wg_slots: host [count] or
+ * NULL (as in mcpd_run_stats). */
 int mcpd_batch_config(const mcpd_batch *batch, uint32_t *wg_per_cu, uint32_t *ticket_slots,
-                      uint32_t *lanes, uint32_t *placement);
+                      uint32_t *lanes, uint32_t *placement, uint32_t *wg_slots);
 
 /* Integer bucket sums of instance `index` from the last run, laid out as
  * opts.bucket_sum / bucket_sumsq of mcpd_run_unbiased (host [rows * n] and

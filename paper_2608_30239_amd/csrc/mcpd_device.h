@@ -37,7 +37,10 @@ __host__ __device__ constexpr int fmt_row_bytes(int f)
 // Lanes per workgroup; also the stride of the lane-fastest state layout.
 constexpr uint32_t WG_LANES = 256;
 
-enum Place : uint32_t { PLACE_STATE_LDS = 1, PLACE_TABLES_LDS = 2 };
+enum Place : uint32_t { PLACE_STATE_LDS = 1, PLACE_TABLES_LDS = 2, PLACE_COOP = 4 };
+
+// Wavefronts of a workgroup of the cooperative kernel (one slot each).
+constexpr uint32_t COOP_WAVES_PER_WG = WG_LANES / 64;
 
 // One instance of a launch, in device memory.  The kernel reads it with
 // scalar loads after a workgroup has taken a ticket for the instance.
@@ -53,6 +56,8 @@ struct InstDesc {
     int32_t n, m;
     uint32_t abits, row_bytes, thr_len;
     uint32_t words_bits, words_cnt;   // per-lane state words (bit pairs, count pairs)
+    uint32_t lanes;         // slots a workgroup runs at once: active lanes (the LDS state
+                            // stride) of the lane kernel, or its wavefronts in the cooperative one
     // Run parameters.
     uint64_t B;             // per-slot horizon
     uint32_t capmax;        // draws after which an unmet pair stops
@@ -65,10 +70,11 @@ struct InstDesc {
     // Placement in the launch's dynamic LDS (dword offsets).
     uint32_t place;         // Place bits
     uint32_t lds_hist, lds_tab;
+    uint32_t lds_state, wave_words;   // cooperative kernel: first wave's state, words per wave
     uint32_t tab_off_thr, tab_off_alias, tab_off_rows, tab_bytes;   // within the table block (bytes)
     // Outputs (zeroed before the launch).
     int64_t *S1;            // [nbuckets * n]
-    uint64_t *S2;           // [nbuckets * n * 2]
+    uint64_t *S2;           // [nbuckets * n * 3]: limbs of the 128-bit sums of squares
     uint64_t *hist;         // [hist_bins]
     uint64_t *stats;        // [ST_COUNT]
     uint32_t *next_slot;    // slot counter
@@ -106,9 +112,10 @@ enum ErrFlag { ERR_BUCKETS = 1 };
 
 // Launch the sampler over a batch (defined in mcpd_sampler.hip); fmt is the
 // row format every instance's rows use.  Returns a hipError_t value as int.
-int launch_sampler(const LaunchArgs &a, int fmt, int grid, size_t lds_bytes, void *stream);
+// coop: the cooperative kernel (one slot per wavefront, state in LDS).
+int launch_sampler(const LaunchArgs &a, int fmt, int grid, size_t lds_bytes, void *stream, bool coop);
 template <int F>
-int launch_sampler_fmt(const LaunchArgs &a, int grid, size_t lds_bytes, void *stream);
+int launch_sampler_fmt(const LaunchArgs &a, int grid, size_t lds_bytes, void *stream, bool coop);
 
 // Zero n64 64-bit words at p (a kernel, so that it can sit in a captured
 // graph).  Returns a hipError_t value as int.

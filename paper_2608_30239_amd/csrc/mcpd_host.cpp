@@ -276,21 +276,35 @@ struct Item {
 // Tuning knobs of a launch (results never depend on them).
 struct Config {
     uint32_t wg_per_cu = 1;   // workgroups of 256 lanes per compute unit
-    uint32_t spl = 1;         // slots per lane one ticket stands for
+    uint32_t spl = 1;         // slots per lane (or per wavefront) one ticket stands for
+    uint32_t narrow = 8;      // least lanes of a narrow LDS layout (0 = none)
+    bool coop = false;        // the cooperative kernel (one slot per wavefront)
 };
+
+// Most workgroups of the cooperative kernel per CU (its registers allow 7
+// wavefronts per SIMD).
+constexpr uint32_t COOP_MAX_WG = 7;
 
 // Placement of one instance in a workgroup's LDS of `budget` bytes.
 struct Layout {
-    uint32_t words_bits, words_cnt, place, lds_hist, lds_tab;
+    uint32_t words_bits, words_cnt, lanes, place, lds_hist, lds_tab, lds_state, wave_words;
     uint32_t off_thr, off_alias, off_rows, tab_bytes;
     size_t used;
 };
 
-int layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan, Layout &L)
+// Placement of one instance in a workgroup's LDS of `budget` bytes.  The
+// chain state goes to LDS for all 256 lanes when it fits, else (narrow_min
+// > 0) for as many lanes as fit, at least narrow_min; a narrow workgroup
+// runs fewer slots at once but every step stays in LDS.  The tables go to
+// LDS when they fit beside the state (for a narrow layout: when they cost
+// at most half of its lanes).  Forced plans (1..4) keep their meaning.
+int layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan,
+           uint32_t narrow_min, Layout &L)
 {
     L.words_bits = (uint32_t)((I->n + 15) / 16);
     L.words_cnt = (uint32_t)((I->m + 1) / 2);
-    const size_t state = ((size_t)L.words_bits + L.words_cnt) * WG_LANES * 4u;
+    const size_t per_lane = ((size_t)L.words_bits + L.words_cnt) * 4u;
+    const size_t full = per_lane * WG_LANES;
     const size_t hist = align16((size_t)hist_bins * 4u);
     L.off_thr = 0;
     L.off_alias = (uint32_t)align16((size_t)I->thr_len * 8u);
@@ -298,31 +312,75 @@ int layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, u
     const size_t tab = align16((size_t)L.off_rows + (size_t)I->n * fmt_row_bytes(fmt));
     L.tab_bytes = (uint32_t)std::min<size_t>(tab, 0xFFFFFFFFu);
     if (hist > budget) return fail(MCPD_EINVAL, "hist_bins too large for LDS");
-    bool sl, tl;
+    auto lanes_in = [&](size_t room) { return (size_t)std::min<size_t>(WG_LANES, room / per_lane); };
+    const size_t lanes_tab = budget >= hist + tab ? lanes_in(budget - hist - tab) : 0;
+    const size_t lanes_no = lanes_in(budget - hist);
+    bool sl = false, tl = false;
+    size_t lanes = WG_LANES;
     if (plan == 0) {
-        sl = tl = true;
-        if (state + hist + tab > budget) {
-            tl = false;
-            if (state + hist > budget) { sl = false; tl = hist + tab <= budget; }
+        if (full + hist + tab <= budget) {
+            sl = tl = true;
+        } else if (full + hist <= budget) {
+            sl = true;
+        } else if (narrow_min && lanes_tab >= narrow_min && 2 * lanes_tab >= lanes_no) {
+            sl = tl = true;
+            lanes = lanes_tab;
+        } else if (narrow_min && lanes_no >= narrow_min) {
+            sl = true;
+            lanes = lanes_no;
+        } else {
+            tl = hist + tab <= budget;
         }
     } else {
         sl = plan <= 2;
         tl = plan == 1 || plan == 3;
-        if ((sl ? state : 0) + hist + (tl ? tab : 0) > budget)
+        if (sl) {
+            lanes = tl ? lanes_tab : lanes_no;
+            if (lanes < WG_LANES && (!narrow_min || lanes < narrow_min))
+                return fail(MCPD_EINVAL, "requested plan does not fit in LDS");
+        } else if (hist + (tl ? tab : 0) > budget) {
             return fail(MCPD_EINVAL, "requested plan does not fit in LDS");
+        }
     }
+    L.lanes = (uint32_t)lanes;
     L.place = (sl ? PLACE_STATE_LDS : 0u) | (tl ? PLACE_TABLES_LDS : 0u);
-    L.lds_hist = sl ? (uint32_t)(state / 4) : 0u;
+    L.lds_hist = sl ? (uint32_t)(per_lane * lanes / 4) : 0u;
     L.lds_tab = L.lds_hist + (uint32_t)(hist / 4);
+    L.lds_state = 0;
+    L.wave_words = 0;
     L.used = (size_t)L.lds_tab * 4 + (tl ? tab : 0);
     return MCPD_OK;
+}
+
+// Placement for the cooperative kernel: the histogram, the tables when they
+// fit, and one chain state per wavefront (words rounded to 16 bytes).
+// Returns false when the wavefronts' states do not fit.
+bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan, Layout &L)
+{
+    if (layout(I, fmt, hist_bins, budget, 4, 0, L)) return false;   // fills the sizes
+    const size_t words = (size_t)L.words_bits + L.words_cnt;
+    const size_t ww = (words + 3) & ~(size_t)3;
+    const size_t states = ww * COOP_WAVES_PER_WG * 4;
+    const size_t hist = align16((size_t)hist_bins * 4u);
+    if (plan == 3 || plan == 4) return false;   // plans that keep the state out of LDS
+    const bool tl = (plan == 0 || plan == 1) && hist + L.tab_bytes + states <= budget;
+    if (plan == 1 && !tl) return false;
+    if (hist + states > budget) return false;
+    L.lanes = COOP_WAVES_PER_WG;
+    L.place = PLACE_STATE_LDS | PLACE_COOP | (tl ? PLACE_TABLES_LDS : 0u);
+    L.lds_hist = 0;
+    L.lds_tab = (uint32_t)(hist / 4);
+    L.lds_state = L.lds_tab + (tl ? L.tab_bytes / 4 : 0u);
+    L.wave_words = (uint32_t)ww;
+    L.used = (size_t)L.lds_state * 4 + states;
+    return true;
 }
 
 // Words of one instance's block of outputs: slot counter, statistics,
 // histogram, S1, S2.
 size_t block_words(size_t n, size_t nb, uint32_t hist_bins)
 {
-    return 1 + ST_COUNT + hist_bins + nb * n + 2 * nb * n;
+    return 1 + ST_COUNT + hist_bins + nb * n + 3 * nb * n;
 }
 
 struct Launch {
@@ -335,6 +393,7 @@ struct Launch {
     int device = 0, cus = 0;
     // plan
     Config cfg;
+    bool coop = false;
     int fmt = 0;
     int grid = 0;
     size_t lds = 0;
@@ -395,6 +454,8 @@ int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool bat
     if (o.u_hi_bits < 1 || o.u_hi_bits > 32) return fail(MCPD_EINVAL, "u_hi_bits must be in 1..32");
     if (o.plan > 4) return fail(MCPD_EINVAL, "plan must be 0..4");
     if (o.wg_per_cu > 8) return fail(MCPD_EINVAL, "wg_per_cu must be 0..8");
+    if (o.narrow_lanes > WG_LANES) return fail(MCPD_EINVAL, "narrow_lanes must be 0..256");
+    if (o.kernel > 2) return fail(MCPD_EINVAL, "kernel must be 0 (auto), 1 (lane) or 2 (cooperative)");
     const uint64_t last_id = (uint64_t)o.instance_id + (batch_ids ? items.size() - 1 : 0);
     if (last_id >= (1u << 24)) return fail(MCPD_EINVAL, "instance ids must be < 2^24");
     for (const Item &it : items) {
@@ -411,17 +472,50 @@ int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool bat
     return MCPD_OK;
 }
 
-// The default configuration: one workgroup per CU when most of the work
-// keeps its chain state in LDS (that already takes the LDS), otherwise as
-// many as the registers allow (more waves hide the latency of global
-// state).
+// Least lanes of a narrow layout from the options (0 = none).
+uint32_t narrow_of(const mcpd_run_opts &o)
+{
+    if (o.narrow_lanes == 0) return 8u;
+    return o.narrow_lanes >= WG_LANES ? 0u : o.narrow_lanes;
+}
+
+// Workgroups per CU at which every instance fits the cooperative layout
+// (0 if none).
+uint32_t coop_wg(const Launch &L, uint32_t most)
+{
+    for (uint32_t wg = most; wg >= 1; --wg) {
+        const size_t budget = (LDS_BYTES / wg - 1024) & ~(size_t)1023;
+        bool all = true;
+        for (const Item &it : L.items) {
+            Layout lay;
+            if (!coop_layout(it.I, L.fmt, L.opts.hist_bins, budget, L.opts.plan, lay)) { all = false; break; }
+        }
+        if (all) return wg;
+    }
+    return 0;
+}
+
+// The default configuration.  The cooperative kernel when every instance's
+// chain states fit it (as many workgroups per CU as LDS and registers
+// allow).  Otherwise the lane kernel: one workgroup per CU when most of the
+// work keeps its chain state in LDS (that already takes the LDS), else as
+// many as the registers allow (more waves hide the latency of global state).
 Config default_config(const Launch &L)
 {
     Config c;
+    c.narrow = narrow_of(L.opts);
+    const uint32_t kernel = L.opts.kernel;
+    const uint32_t cw = kernel == 1 ? 0u : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : COOP_MAX_WG);
+    if (cw) {
+        c.coop = true;
+        c.wg_per_cu = cw;
+        c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 4u;
+        return c;
+    }
     double in_lds = 0, total = 0;
     for (const Item &it : L.items) {
         Layout lay;
-        if (layout(it.I, L.fmt, L.opts.hist_bins, LDS_BYTES - 1024, 0, lay)) continue;
+        if (layout(it.I, L.fmt, L.opts.hist_bins, LDS_BYTES - 1024, 0, narrow_of(L.opts), lay)) continue;
         const double w = (double)it.budget + (double)it.slots;
         total += w;
         if (lay.place & PLACE_STATE_LDS) in_lds += w;
@@ -454,8 +548,14 @@ int plan(Launch &L, const Config &c)
         const Item &it = L.items[i];
         mcpd_instance *I = it.I;
         Layout lay;
-        int rc = layout(I, L.fmt, o.hist_bins, budget, o.plan, lay);
-        if (rc) return rc;
+        if (c.coop) {
+            if (!coop_layout(I, L.fmt, o.hist_bins, budget, o.plan, lay))
+                return fail(MCPD_EINVAL, "an instance's chain states do not fit the cooperative layout");
+        } else {
+            int rc = layout(I, L.fmt, o.hist_bins, budget, o.plan, c.narrow, lay);
+            if (rc) return rc;
+        }
+        int rc;
         const uint32_t *rows = nullptr;
         if ((rc = rows_for(I, L.fmt, &rows))) return rc;
         InstDesc &d = L.desc[i];
@@ -469,6 +569,7 @@ int plan(Launch &L, const Config &c)
         d.thr_len = I->thr_len;
         d.words_bits = lay.words_bits;
         d.words_cnt = lay.words_cnt;
+        d.lanes = lay.lanes;
         d.B = it.budget / it.slots;
         d.cmin = std::max<uint32_t>(it.m, 1u);
         d.capmax = o.max_steps ? (uint32_t)std::max<uint64_t>(o.max_steps, it.m) : 0xFFFFFFFFu;
@@ -482,6 +583,8 @@ int plan(Launch &L, const Config &c)
         d.place = lay.place;
         d.lds_hist = lay.lds_hist;
         d.lds_tab = lay.lds_tab;
+        d.lds_state = lay.lds_state;
+        d.wave_words = lay.wave_words;
         d.tab_off_thr = lay.off_thr;
         d.tab_off_alias = lay.off_alias;
         d.tab_off_rows = lay.off_rows;
@@ -489,6 +592,7 @@ int plan(Launch &L, const Config &c)
         L.lds = std::max(L.lds, lay.used);
         if (!(lay.place & PLACE_STATE_LDS))
             L.gwords = std::max<uint32_t>(L.gwords, lay.words_bits + lay.words_cnt);
+        L.coop = c.coop;
         L.acc_stride = std::max<uint32_t>(L.acc_stride, (uint32_t)I->n);
         L.nb[i] = d.nbuckets;
         L.off[i] = words;
@@ -505,14 +609,16 @@ int plan(Launch &L, const Config &c)
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return L.desc[a].B > L.desc[b].B; });
     L.tickets.clear();
-    const uint64_t per_ticket = (uint64_t)WG_LANES * c.spl;
     for (size_t i : order) {
+        const uint64_t per_ticket = (uint64_t)L.desc[i].lanes * c.spl;
         const uint64_t t = std::max<uint64_t>(1, (L.desc[i].P + per_ticket - 1) / per_ticket);
         for (uint64_t j = 0; j < t; ++j) L.tickets.push_back((uint32_t)i);
     }
     L.grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.cus * c.wg_per_cu, L.tickets.size()));
     const size_t lanes = (size_t)L.grid * WG_LANES;
-    L.list_cap = std::min<uint32_t>(512, std::max<uint32_t>(64, L.acc_stride / 16));
+    // touched-clone lists long enough that large instances rarely fall back
+    // to scanning a whole numerator row at the end of a slot
+    L.list_cap = std::min<uint32_t>(4096, std::max<uint32_t>(64, L.acc_stride / 4));
 
     // Workspace.  Numerator rows stay zero between runs (the kernel clears
     // what it used), so they are cleared only when (re)allocated.
@@ -594,7 +700,7 @@ int enqueue(Launch &L, bool timed)
     int e = launch_fill_zero(L.d_zero, L.zero_words, L.stream);
     if (e != hipSuccess) return hip_fail((hipError_t)e, "zero outputs");
     if (timed) HIP_TRY(hipEventRecord(L.ev0, L.stream));
-    e = launch_sampler(launch_args(L), L.fmt, L.grid, L.lds, L.stream);
+    e = launch_sampler(launch_args(L), L.fmt, L.grid, L.lds, L.stream, L.coop);
     if (e != hipSuccess) return hip_fail((hipError_t)e, "sampler launch");
     if (timed) HIP_TRY(hipEventRecord(L.ev1, L.stream));
     HIP_TRY(hipMemcpyAsync(L.h_out, L.d_zero, L.zero_words * 8, hipMemcpyDeviceToHost, L.stream));
@@ -661,8 +767,8 @@ int finish_item(const Launch &L, size_t i, double *marginals, double *stderr_out
                 const size_t idx = (size_t)r * n + j;
                 const long double nn = (long double)(r + 1);
                 sa += (long double)S1[idx] / nn;
-                const long double v2 =
-                    (long double)S2[2 * idx + 1] * 18446744073709551616.0L + (long double)S2[2 * idx];
+                const long double v2 = (long double)S2[3 * idx + 2] * 18446744073709551616.0L +
+                                       (long double)S2[3 * idx + 1] * 4294967296.0L + (long double)S2[3 * idx];
                 sq += v2 / (nn * nn);
             }
             if (marginals) marginals[j] = (double)(sa / PW);
@@ -696,6 +802,8 @@ int finish_item(const Launch &L, size_t i, double *marginals, double *stderr_out
         stats->lanes = (uint64_t)L.grid * WG_LANES;
         stats->placement = d.place;
         stats->wg_per_cu = L.cfg.wg_per_cu;
+        stats->wg_slots = d.lanes;
+        stats->kernel = L.coop ? 2u : 1u;
         stats->kernel_ms = L.last_ms;
     }
     if (L.opts.strict_cap && st[ST_CAP_HITS]) return fail(MCPD_ECAP, "a retained pair hit the meeting cap");
@@ -717,8 +825,15 @@ int copy_buckets(const Launch &L, size_t i, uint32_t rows, int64_t *sum, uint64_
         std::memcpy(sum, h + L.opts.hist_bins, sizeof(int64_t) * r * n);
     }
     if (sumsq) {
+        // 128-bit sums from the device's limbs: a + b 2^32 + c 2^64
         std::memset(sumsq, 0, sizeof(uint64_t) * 2 * (size_t)rows * n);
-        std::memcpy(sumsq, h + L.opts.hist_bins + (size_t)nb * n, sizeof(uint64_t) * 2 * r * n);
+        const uint64_t *S2 = h + L.opts.hist_bins + (size_t)nb * n;
+        for (size_t idx = 0; idx < r * n; ++idx) {
+            const unsigned __int128 v = (unsigned __int128)S2[3 * idx] + ((unsigned __int128)S2[3 * idx + 1] << 32) +
+                                        ((unsigned __int128)S2[3 * idx + 2] << 64);
+            sumsq[2 * idx] = (uint64_t)v;
+            sumsq[2 * idx + 1] = (uint64_t)(v >> 64);
+        }
     }
     return MCPD_OK;
 }
@@ -920,6 +1035,7 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
     L.slot_records = opts.slot_nstar || opts.slot_units;
     L.fmt = pick_format(I->m > 127, I->dmax);
     Config c = default_config(L);
+    if (opts.kernel == 2 && !c.coop) return fail(MCPD_EINVAL, "the chain states do not fit the cooperative kernel");
     if ((rc = plan(L, c))) return rc;
     if ((rc = execute(L, seed, false))) return rc;
     if (L.slot_records && (rc = copy_slot_records(L, 0, opts.slot_nstar, opts.slot_units))) return rc;
@@ -979,7 +1095,9 @@ int mcpd_batch_create(mcpd_instance *const *insts, int32_t count, const uint64_t
         HIP_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
         L.own_stream = true;
     }
-    if ((rc = plan(L, default_config(L)))) return rc;
+    const Config c = default_config(L);
+    if (opts.kernel == 2 && !c.coop) return fail(MCPD_EINVAL, "the chain states do not fit the cooperative kernel");
+    if ((rc = plan(L, c))) return rc;
     *out = b.release();
     return MCPD_OK;
 }
@@ -1009,16 +1127,36 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
     // Candidates: workgroups per CU (registers allow three waves of the
     // sampler per SIMD) x slots per lane per ticket.
     std::vector<Config> cands;
-    const uint32_t wgs[] = {1, 2, 3};
-    const uint32_t spls[] = {1, 2, 4};
-    for (uint32_t w : wgs) {
-        if (L.opts.wg_per_cu && w != L.opts.wg_per_cu) continue;
-        for (uint32_t s : spls) {
-            if (L.opts.ticket_slots && s != L.opts.ticket_slots) continue;
-            Config c;
-            c.wg_per_cu = w;
-            c.spl = s;
-            cands.push_back(c);
+    if (L.opts.kernel != 2) {
+        const uint32_t wgs[] = {1, 2};
+        const uint32_t narrows[] = {8, 0};
+        for (uint32_t w : wgs) {
+            if (L.opts.wg_per_cu && w != L.opts.wg_per_cu) continue;
+            for (uint32_t nw : narrows) {
+                if (L.opts.narrow_lanes && nw != narrow_of(L.opts)) continue;
+                Config c;
+                c.wg_per_cu = w;
+                c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 1u;
+                c.narrow = nw;
+                cands.push_back(c);
+            }
+        }
+    }
+    if (L.opts.kernel != 1) {
+        const uint32_t top = coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : COOP_MAX_WG);
+        if (top) {
+            const uint32_t wgs[] = {top, (top + 1) / 2};
+            const uint32_t spls[] = {2, 8};
+            for (int wi = 0; wi < (top > 1 ? 2 : 1); ++wi) {
+                for (uint32_t sp : spls) {
+                    if (L.opts.ticket_slots && sp != L.opts.ticket_slots) continue;
+                    Config c;
+                    c.coop = true;
+                    c.wg_per_cu = wgs[wi];
+                    c.spl = sp;
+                    cands.push_back(c);
+                }
+            }
         }
     }
     Config best = L.cfg;
@@ -1030,7 +1168,7 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
         if (rc) return rc;
         if ((rc = execute(L, seed, false))) return rc;
         const double ms = L.last_ms;
-        if (entries && done < cap) entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, ms};
+        if (entries && done < cap) entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, c.narrow, c.coop ? 2u : 1u, ms};
         ++done;
         if (ms < best_ms) { best_ms = ms; best = c; }
     }
@@ -1040,7 +1178,7 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
 }
 
 int mcpd_batch_config(const mcpd_batch *b, uint32_t *wg_per_cu, uint32_t *ticket_slots, uint32_t *lanes,
-                      uint32_t *placement)
+                      uint32_t *placement, uint32_t *wg_slots)
 {
     using namespace mcpd::host;
     if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
@@ -1048,8 +1186,10 @@ int mcpd_batch_config(const mcpd_batch *b, uint32_t *wg_per_cu, uint32_t *ticket
     if (wg_per_cu) *wg_per_cu = L.cfg.wg_per_cu;
     if (ticket_slots) *ticket_slots = L.cfg.spl;
     if (lanes) *lanes = (uint32_t)L.grid * mcpd::WG_LANES;
-    if (placement)
-        for (size_t i = 0; i < L.desc.size(); ++i) placement[i] = L.desc[i].place;
+    for (size_t i = 0; i < L.desc.size(); ++i) {
+        if (placement) placement[i] = L.desc[i].place;
+        if (wg_slots) wg_slots[i] = L.desc[i].lanes;
+    }
     return MCPD_OK;
 }
 

@@ -151,7 +151,9 @@ struct Sampler {
     const LaunchArgs &a;
     DescPtr D;
     uint32_t k0, k1;        // the key of the random numbers
-    uint32_t *st;           // this workgroup's state base (LDS or global)
+    uint32_t *st;           // this workgroup's state base (LDS or global): bit words
+    uint32_t *cst;          // its count words (st + words_bits * stride)
+    uint32_t stride;        // state words of one index for all lanes (lane-fastest)
     const uint64_t *thr;    // tables (LDS copies or global)
     const uint32_t *alias;
     const uint32_t *rows;
@@ -161,8 +163,8 @@ struct Sampler {
     uint64_t *ls;           // this lane's statistics
     uint32_t *hist_lds;
 
-    __device__ __forceinline__ uint32_t &bits(uint32_t w) const { return st[w * WG + lane]; }
-    __device__ __forceinline__ uint32_t &cnt(uint32_t q) const { return st[(D->words_bits + q) * WG + lane]; }
+    __device__ __forceinline__ uint32_t &bits(uint32_t w) const { return st[w * stride + lane]; }
+    __device__ __forceinline__ uint32_t &cnt(uint32_t q) const { return cst[q * stride + lane]; }
 
     // Statistic slots and spill rows belong to one lane: workgroup-scope
     // atomics keep them in the L2 of the lane's XCD instead of memory.
@@ -178,7 +180,7 @@ struct Sampler {
     __device__ __forceinline__ void reset_state() const
     {
         const uint32_t nw = D->words_bits + D->words_cnt;
-        for (uint32_t w = 0; w < nw; ++w) st[w * WG + lane] = 0u;
+        for (uint32_t w = 0; w < nw; ++w) st[w * stride + lane] = 0u;
     }
 
     // First draw count at which after_step has anything to decide: the end of
@@ -372,6 +374,11 @@ struct Sampler {
         }
     }
 
+    // Add a slot's numerator to its N* bucket: S1 += V and the square V^2 =
+    // h 2^64 + l as three 64-bit limbs, S2 += (l mod 2^32, l >> 32, h).  All
+    // no-return atomics; the host rebuilds the 128-bit sums (the limb sums
+    // stay exact while there are fewer than 2^32 slots and the high words
+    // sum below 2^64).
     __device__ __forceinline__ void emit(uint32_t nstar, uint32_t j, int64_t v) const
     {
         if (nstar > D->nbuckets) {
@@ -383,12 +390,26 @@ struct Sampler {
         const uint64_t u = v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
         const uint64_t lo = u * u;
         const uint64_t hi = __umul64hi(u, u);
-        const unsigned long long old =
-            atomicAdd(reinterpret_cast<unsigned long long *>(D->S2 + 2 * idx), (unsigned long long)lo);
-        const uint64_t carry = ((uint64_t)old + lo < (uint64_t)old) ? 1u : 0u;
-        if (hi + carry)
-            atomicAdd(reinterpret_cast<unsigned long long *>(D->S2 + 2 * idx + 1),
-                      (unsigned long long)(hi + carry));
+        unsigned long long *q = reinterpret_cast<unsigned long long *>(D->S2 + 3 * idx);
+        atomicAdd(q, (unsigned long long)(lo & 0xFFFFFFFFull));
+        if (lo >> 32) atomicAdd(q + 1, (unsigned long long)(lo >> 32));
+        if (hi) atomicAdd(q + 2, (unsigned long long)hi);
+    }
+
+    // Take (and clear) the spilled numerators of up to 8 clones at once, so
+    // that their round trips overlap, then emit the nonzero ones.
+    __device__ __forceinline__ void take8(uint32_t nstar, const uint32_t j[8], uint32_t cnt) const
+    {
+        int64_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            v[q] = (uint32_t)q < cnt ? (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j[q]),
+                                                                      (uint64_t)0, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_WORKGROUP)
+                                     : 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (v[q] != 0) emit(nstar, j[q], v[q]);
     }
 
     __device__ __forceinline__ void flush_slot(Lane &s) const
@@ -401,19 +422,25 @@ struct Sampler {
             s.cval[e] = 0;
         }
         if (s.lc > 0) {
+            uint32_t j[8];
             if (s.lc <= a.list_cap) {
-                for (uint32_t e = 0; e < s.lc; ++e) {
-                    const uint32_t j = __hip_atomic_load(list + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
-                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (v != 0) emit(nstar, j, v);
+                for (uint32_t e0 = 0; e0 < s.lc; e0 += 8) {
+                    const uint32_t cnt = s.lc - e0 < 8u ? s.lc - e0 : 8u;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        j[q] = (uint32_t)q < cnt ? __hip_atomic_load(list + e0 + q, __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_WORKGROUP)
+                                                 : 0u;
+                    take8(nstar, j, cnt);
                 }
             } else {
                 stat_add(ST_LIST_OVERFLOWS, 1);
-                for (uint32_t j = 0; j < (uint32_t)D->n; ++j) {
-                    const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
-                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (v != 0) emit(nstar, j, v);
+                const uint32_t n = (uint32_t)D->n;
+                for (uint32_t j0 = 0; j0 < n; j0 += 8) {
+                    const uint32_t cnt = n - j0 < 8u ? n - j0 : 8u;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) j[q] = j0 + (uint32_t)q;
+                    take8(nstar, j, cnt);
                 }
             }
         }
@@ -507,11 +534,17 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_
     for (int i = 0; i < ST_COUNT; ++i) ls[i] = 0;
     __syncthreads();
 
+    // State in LDS is laid out for the instance's active lanes (a narrow
+    // workgroup keeps large states in LDS); in global memory for all 256.
+    const uint32_t stride = SL ? D->lanes : WG;
+    uint32_t *st = SL ? smem : a.gstate + (size_t)blockIdx.x * a.gwords * WG;
     Sampler<SL, TL, F> S{a,
                          D,
                          k0,
                          k1,
-                         SL ? smem : a.gstate + (size_t)blockIdx.x * a.gwords * WG,
+                         st,
+                         st + (size_t)D->words_bits * stride,
+                         stride,
                          TL ? reinterpret_cast<const uint64_t *>(tab + D->tab_off_thr / 4) : D->thr,
                          TL ? tab + D->tab_off_alias / 4 : D->alias,
                          TL ? tab + D->tab_off_rows / 4 : D->rows,
@@ -521,7 +554,7 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_
                          ls,
                          hist_lds};
     Lane s;
-    s.mode = MODE_NEED_SLOT;
+    s.mode = lane < D->lanes ? MODE_NEED_SLOT : MODE_DONE;
     s.p = s.r = s.t = s.nret = s.tau = s.target = s.lim = 0;
     s.mu = 0;
     s.sgn = 1;
@@ -667,25 +700,482 @@ __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
     }
 }
 
+// ------------------------------------------------------------ cooperative
+// One wavefront runs one slot at a time.  Each iteration the 64 lanes draw
+// the next 64 updates of the same pair speculatively against the current
+// state; a ballot finds the first lane whose update changes either chain.
+// Every lane before it changed nothing, so their updates were made on the
+// exact state and stand; the first changing lane's update stands too and is
+// applied; the lanes after it are dropped and redrawn in the next iteration.
+// The committed draws and decisions are exactly those of the one-lane
+// sampler.  The chain state of a slot (0.5 KB for 1298 clones and 97 pools)
+// is small enough that every wave of a CU keeps its own in LDS, and a slot
+// whose pair takes very long to meet advances tens of draws per iteration.
+constexpr uint32_t COOP_WAVES = WG / 64;   // wavefronts per workgroup
+
+struct WaveSlot {
+    uint32_t p, r, t, nret, tau, target, lim, lc, f0, f1;
+    int32_t mu, sgn;
+    uint64_t S;
+};
+
+template <bool TL, int F>
+struct Coop {
+    const LaunchArgs &a;
+    DescPtr D;
+    uint32_t k0, k1;
+    uint32_t *st;           // this wave's bit words (LDS)
+    uint32_t *cst;          // its count words
+    const uint64_t *thr;
+    const uint32_t *alias;
+    const uint32_t *rows;
+    uint32_t lane;          // lane within the wave
+    int64_t *acc;           // this wave's numerator row
+    uint32_t *list;         // its touched list
+    uint32_t *hist_lds;
+    uint64_t *ls;           // this wave's statistics (global, written by lane 0)
+
+    __device__ __forceinline__ void stat_add(int i, uint64_t v) const
+    {
+        if (lane == 0) __hip_atomic_fetch_add(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __device__ __forceinline__ void stat_max(int i, uint64_t v) const
+    {
+        if (lane == 0) __hip_atomic_fetch_max(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
+    __device__ __forceinline__ uint32_t site(uint32_t sw) const
+    {
+        const uint32_t cb = 32u - D->abits;
+        const uint32_t col = sw >> cb;
+        const uint32_t aw = alias[col];
+        const uint32_t kmask = (1u << cb) - 1u;
+        return (sw & kmask) < (aw & kmask) ? col : (aw >> cb);
+    }
+
+    __device__ __forceinline__ uint64_t low_bits(const WaveSlot &s, uint32_t t) const
+    {
+        uint32_t o[4];
+        philox10(t, s.r, s.p, D->g | (1u << 24), k0, k1, o);
+        const uint64_t v = ((uint64_t)o[0] << 32) | (uint64_t)o[1];
+        return v >> (11u + a.ubits);
+    }
+
+    __device__ __forceinline__ uint32_t decide(const WaveSlot &s, uint32_t t, uint32_t hw, uint64_t T, bool &have_lo,
+                                               uint64_t &lo) const
+    {
+        const uint32_t b = a.ubits;
+        const uint32_t hb = hw >> (32u - b);
+        const uint32_t th = (uint32_t)(T >> (53u - b));
+        if (hb != th) return hb < th ? 1u : 0u;
+        if (!have_lo) { lo = low_bits(s, t); have_lo = true; }
+        return lo <= (T & ((1ull << (53u - b)) - 1ull)) ? 1u : 0u;
+    }
+
+    __device__ __forceinline__ void wave_fence() const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+
+    __device__ __forceinline__ void reset_state() const
+    {
+        const uint32_t nw = D->words_bits + D->words_cnt;
+        for (uint32_t w = lane; w < nw; w += 64u) st[w] = 0u;
+        wave_fence();
+    }
+
+    // The numerator of clone j (wave-wide add from one lane), recorded in the
+    // touched list by the caller.
+    __device__ __forceinline__ void add(uint32_t j, uint64_t v) const
+    {
+        __hip_atomic_fetch_add(reinterpret_cast<uint64_t *>(acc + j), v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
+    __device__ __forceinline__ void emit(uint32_t nstar, uint32_t j, int64_t v) const
+    {
+        if (nstar > D->nbuckets) {
+            atomicOr(&a.ctrl[1], (uint32_t)ERR_BUCKETS);
+            return;
+        }
+        const size_t idx = (size_t)(nstar - 1u) * (size_t)D->n + j;
+        atomicAdd(reinterpret_cast<unsigned long long *>(D->S1 + idx), (unsigned long long)v);
+        const uint64_t u = v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
+        const uint64_t lo = u * u;
+        const uint64_t hi = __umul64hi(u, u);
+        unsigned long long *q = reinterpret_cast<unsigned long long *>(D->S2 + 3 * idx);
+        atomicAdd(q, (unsigned long long)(lo & 0xFFFFFFFFull));
+        if (lo >> 32) atomicAdd(q + 1, (unsigned long long)(lo >> 32));
+        if (hi) atomicAdd(q + 2, (unsigned long long)hi);
+    }
+
+    // Boundary term G(C) Delta_j(C) of a pair stopped by the cap, lanes over
+    // the bit words; the touched list is given up (the flush scans the row).
+    __device__ void truncation(WaveSlot &s) const
+    {
+        const uint32_t C = s.t;
+        if (C < D->k + 1u) return;
+        const uint64_t G = gsum(C, D->k, D->ell, D->W);
+        for (uint32_t w = lane; w < D->words_bits; w += 64u) {
+            const uint32_t word = st[w];
+            uint32_t mis = (word ^ (word >> 1)) & 0x55555555u;
+            while (mis) {
+                const uint32_t b = __builtin_ctz(mis);
+                mis &= mis - 1u;
+                const uint64_t v = ((word >> b) & 1u) ? G : (uint64_t)0 - G;
+                add(w * 16u + (b >> 1), s.sgn > 0 ? v : (uint64_t)0 - v);
+            }
+        }
+        s.lc = a.list_cap + 1u;
+    }
+
+    __device__ void flush_slot(WaveSlot &s) const
+    {
+        const uint32_t nstar = s.nret;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (s.lc <= a.list_cap) {
+            for (uint32_t e = lane; e < s.lc; e += 64u) {
+                const uint32_t j = __hip_atomic_load(list + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (v != 0) emit(nstar, j, v);
+            }
+        } else {
+            stat_add(ST_LIST_OVERFLOWS, 1);
+            for (uint32_t j = lane; j < (uint32_t)D->n; j += 64u) {
+                const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (v != 0) emit(nstar, j, v);
+            }
+        }
+        if (lane == 0) {
+            if (D->slot_nstar) D->slot_nstar[s.p] = nstar;
+            if (D->slot_units) D->slot_units[s.p] = s.S;
+        }
+        stat_max(ST_NSTAR_MAX, nstar);
+    }
+
+    __device__ __forceinline__ void begin_rollback(WaveSlot &s, uint32_t draws) const
+    {
+        stat_add(ST_REPS_ABORTED, 1);
+        stat_add(ST_ROLLBACK_UNITS, draws);
+        stat_add(ST_PROGRESS, 2ull * draws);
+        s.target = draws;
+        s.sgn = -1;
+    }
+
+    // After the draw count reached the replication's limit: 0 = keep going,
+    // 1 = next replication (or replay), 2 = slot finished.
+    __device__ int after_step(WaveSlot &s) const
+    {
+        const uint32_t d = s.t;
+        const bool capped = (s.tau == 0u) && (d >= D->capmax);
+        const bool ended = capped || (s.tau != 0u && d >= D->ell);
+        if (s.sgn < 0) {
+            if (d == s.target) {
+                if (capped) truncation(s);
+                flush_slot(s);
+                return 2;
+            }
+            return 0;
+        }
+        if (ended) {
+            if (capped) truncation(s);
+            const uint64_t C = d;
+            const bool retained = (s.r == 1u) || (s.S + C <= D->B);
+            if (!retained) { begin_rollback(s, d); return 1; }
+            s.S += C;
+            s.nret += 1u;
+            stat_add(ST_RETAINED_UNITS, C);
+            stat_add(ST_PROGRESS, C);
+            stat_add(ST_REPS_RETAINED, 1);
+            if (capped) {
+                stat_add(ST_CAP_HITS, 1);
+                stat_add(ST_SINGLE_SITE, 1 + 2 * (C - 1));
+            } else {
+                const uint64_t mt = s.tau < d ? s.tau : d;
+                stat_add(ST_SINGLE_SITE, 1 + 2 * (mt - 1) + (C - mt));
+                stat_add(ST_TAU_SUM, s.tau);
+                stat_max(ST_TAU_MAX, s.tau);
+                uint32_t bin = s.tau / D->hist_width;
+                if (bin >= a.hist_bins) bin = a.hist_bins - 1u;
+                if (lane == 0) atomicAdd(hist_lds + bin, 1u);
+            }
+            if (s.r == 1u && C > D->B) stat_add(ST_ZERO_COMPLETION, 1);
+            if (!a.refill || s.S >= D->B || s.S + D->cmin > D->B) {
+                flush_slot(s);
+                return 2;
+            }
+            return 1;
+        }
+        if (s.r >= 2u && (uint64_t)d > D->B - s.S) {
+            begin_rollback(s, d);
+            return 1;
+        }
+        return 0;
+    }
+
+    // One iteration: up to `span` draws from s.t, of which a prefix stands.
+    __device__ __forceinline__ void iterate(WaveSlot &s, uint32_t span)
+    {
+        using R = Row<F>;
+        const uint32_t t = s.t + lane;
+        const bool act = lane < span;
+        const bool updY = (s.tau == 0u) && (t > 0u);
+        uint32_t blk[4];
+        philox10(t >> 1, s.r, s.p, D->g, k0, k1, blk);
+        const uint32_t sw = (t & 1u) ? blk[2] : blk[0];
+        const uint32_t hw = (t & 1u) ? blk[3] : blk[1];
+        const uint32_t I = act ? site(sw) : 0u;
+        Row<F> rc;
+        rc.load(rows, I);
+        const uint32_t bw_idx = I >> 4;
+        const uint32_t bw = st[bw_idx];
+        uint32_t cw[R::NE];
+#pragma unroll
+        for (int e = 0; e < R::NE; ++e) {
+            const uint32_t v = rc.raw(e);
+            cw[e] = cst[(R::valid(v) ? R::pool(v) : 0u) >> 1];
+        }
+        const uint32_t sh = (I & 15u) << 1;
+        const uint32_t xi = (bw >> sh) & 1u;
+        const uint32_t yi = (bw >> (sh + 1u)) & 1u;
+        uint32_t patX = 0, lenX = 0, patY = 0, lenY = 0;
+#pragma unroll
+        for (int e = 0; e < R::NE; ++e) {
+            const uint32_t v = rc.raw(e);
+            const bool ok = R::valid(v);
+            const uint32_t o = R::outcome(v);
+            const uint32_t c = cw[e] >> ((R::pool(v) & 1u) << 4);
+            const bool fx = ok && (c & 0xFFu) == xi;
+            const bool fy = ok && ((c >> 8) & 0xFFu) == yi;
+            patX = fx ? ((patX << 1) | o) : patX;
+            lenX += fx ? 1u : 0u;
+            patY = fy ? ((patY << 1) | o) : patY;
+            lenY += fy ? 1u : 0u;
+        }
+        bool have_lo = false;
+        uint64_t lo = 0;
+        const uint32_t ix = (1u << lenX) - 1u + patX;
+        const uint32_t xn = decide(s, t, hw, thr[ix], have_lo, lo);
+        uint32_t yn = yi;
+        if (updY) {
+            const uint32_t iy = (1u << lenY) - 1u + patY;
+            yn = (iy == ix) ? xn : decide(s, t, hw, thr[iy], have_lo, lo);
+        }
+        const bool flip = act && (xn != xi || yn != yi);
+        const uint64_t m = __ballot(flip);
+        if (m == 0) {
+            // at the pre-lag draw (span 1) a pair that did not move meets at t = 1
+            if (s.tau == 0u && s.mu == 0) s.tau = s.t + 1u;
+            s.t += span;
+            return;
+        }
+        const uint32_t f = (uint32_t)__builtin_ctzll(m);
+        int dmu = 0;
+        uint32_t ev = 0;
+        if (lane == f) {
+            const int dx = (int)xn - (int)xi;
+            const int dy = (int)yn - (int)yi;
+            st[bw_idx] = bw ^ ((uint32_t)(dx != 0) << sh) ^ ((uint32_t)(dy != 0) << (sh + 1u));
+#pragma unroll
+            for (int e = 0; e < R::NE; ++e) {
+                const uint32_t v = rc.raw(e);
+                if (!R::valid(v)) continue;
+                const uint32_t j = R::pool(v);
+                const uint32_t cs = (j & 1u) << 4;
+                cst[j >> 1] += ((uint32_t)dx << cs) + ((uint32_t)dy << (cs + 8u));
+            }
+            if (s.tau == 0u) dmu = (int)(xn != yn) - (int)(xi != yi);
+            uint64_t val = 0;
+            const uint32_t te = t + 1u;
+            if (dx != 0 && te <= D->ell) {
+                const uint32_t from = te > D->k ? te : D->k;
+                val += (uint64_t)(int64_t)dx * (uint64_t)(D->ell - from + 1u);
+            }
+            if (updY && t >= D->k + 1u && dx != dy)
+                val -= (uint64_t)(int64_t)(dx - dy) * gsum(t, D->k, D->ell, D->W);
+            if (val != 0) {
+                add(I, s.sgn > 0 ? val : (uint64_t)0 - val);
+                ev = 1;
+            }
+        }
+        // f is wave-uniform: read lane f's results into scalar registers
+        dmu = __builtin_amdgcn_readlane(dmu, (int)f);
+        ev = __builtin_amdgcn_readlane(ev, (int)f);
+        const uint32_t If = __builtin_amdgcn_readlane(I, (int)f);
+        if (ev && If != s.f0 && If != s.f1) {
+            if (lane == 0 && s.lc < a.list_cap)
+                __hip_atomic_store(list + s.lc, If, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            s.lc += 1u;
+            s.f1 = s.f0;
+            s.f0 = If;
+        }
+        if (s.tau == 0u) {
+            s.mu += dmu;
+            if (s.mu == 0) s.tau = s.t + f + 1u;
+        }
+        s.t += f + 1u;
+        wave_fence();
+    }
+};
+
+template <bool TL, int F>
+__device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32_t *smem, uint32_t k0, uint32_t k1)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    uint32_t *hist_lds = smem + D->lds_hist;
+    uint32_t *tab = smem + D->lds_tab;
+    for (uint32_t b = tid; b < a.hist_bins; b += WG) hist_lds[b] = 0u;
+    if (TL) {
+        copy_to_lds(tab + D->tab_off_thr / 4, D->thr, D->thr_len * 2u);
+        copy_to_lds(tab + D->tab_off_alias / 4, D->alias, 1u << D->abits);
+        copy_to_lds(tab + D->tab_off_rows / 4, D->rows, (uint32_t)D->n * D->row_bytes / 4u);
+    }
+    __syncthreads();
+    uint32_t *st = smem + D->lds_state + wave * D->wave_words;
+    const size_t gw = (size_t)blockIdx.x * COOP_WAVES + wave;
+    uint64_t *ls = a.lane_stats + gw * ST_COUNT;
+    if (lane < (uint32_t)ST_COUNT) ls[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    Coop<TL, F> C{a,
+                  D,
+                  k0,
+                  k1,
+                  st,
+                  st + D->words_bits,
+                  TL ? reinterpret_cast<const uint64_t *>(tab + D->tab_off_thr / 4) : D->thr,
+                  TL ? tab + D->tab_off_alias / 4 : D->alias,
+                  TL ? tab + D->tab_off_rows / 4 : D->rows,
+                  lane,
+                  a.acc + gw * (size_t)a.acc_stride,
+                  a.lists + gw * (size_t)a.list_cap,
+                  hist_lds,
+                  ls};
+    const uint32_t P = D->P;
+    const uint32_t ell = D->ell, capmax = D->capmax;
+    for (;;) {
+        uint32_t p = 0;
+        if (lane == 0) p = atomicAdd(D->next_slot, 1u);
+        p = __builtin_amdgcn_readfirstlane(p);
+        if (p >= P) break;
+        WaveSlot s;
+        s.p = p;
+        s.r = s.t = s.nret = s.tau = s.target = s.lim = s.lc = 0;
+        s.f0 = s.f1 = NO_TAG;
+        s.mu = 0;
+        s.sgn = 1;
+        s.S = 0;
+        for (;;) {   // replications (and replays)
+            if (s.sgn > 0) {
+                s.r += 1u;
+                C.stat_add(ST_REPS_STARTED, 1);
+            }
+            C.reset_state();
+            s.t = 0;
+            s.tau = 0;
+            s.mu = 0;
+            uint32_t lim = ell < capmax ? ell : capmax;
+            if (s.sgn < 0 && s.target < lim) lim = s.target;
+            if (s.r >= 2u) {
+                const uint64_t ab = D->B - s.S + 1u;
+                if (ab < (uint64_t)lim) lim = (uint32_t)ab;
+            }
+            int next = 0;
+            while (next == 0) {
+                // the next draw count at which something may have to be decided
+                uint32_t stop = capmax;
+                if (s.sgn < 0 && s.target < stop) stop = s.target;
+                if (s.r >= 2u) {
+                    const uint64_t ab = D->B - s.S + 1u;
+                    if (ab < (uint64_t)stop) stop = (uint32_t)ab;
+                }
+                if (s.t < ell && ell < stop) stop = ell;
+                uint32_t span = stop - s.t;
+                if (span > 64u) span = 64u;
+                if (s.t == 0u) span = 1u;
+                C.iterate(s, span);
+                if (s.t >= lim) next = C.after_step(s);
+            }
+            if (next == 2) break;
+        }
+    }
+    // statistics: one atomic per counter and wave
+    if (lane < (uint32_t)ST_COUNT) {
+        const uint64_t v = __hip_atomic_load(ls + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (v) {
+            if (lane == ST_TAU_MAX || lane == ST_NSTAR_MAX)
+                atomicMax(reinterpret_cast<unsigned long long *>(D->stats + lane), (unsigned long long)v);
+            else
+                atomicAdd(reinterpret_cast<unsigned long long *>(D->stats + lane), (unsigned long long)v);
+        }
+    }
+    __syncthreads();
+    uint64_t *hist = D->hist;
+    for (uint32_t b = tid; b < a.hist_bins; b += WG)
+        if (hist_lds[b]) atomicAdd(reinterpret_cast<unsigned long long *>(hist + b), (unsigned long long)hist_lds[b]);
+    __syncthreads();
+}
+
+// The cooperative variant of the persistent kernel (chain state always in
+// LDS, one slot per wave).
+template <int F>
+__global__ void __launch_bounds__(256) coop_kernel(LaunchArgs a)
+{
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t sh_item, sh_skip;
+    const uint64_t seed = *(const __attribute__((address_space(4))) uint64_t *)a.seed;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    DescPtr descs = (DescPtr)a.inst;
+    const __attribute__((address_space(4))) uint32_t *tickets =
+        (const __attribute__((address_space(4))) uint32_t *)a.tickets;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t it = atomicAdd(&a.ctrl[0], 1u);
+            uint32_t skip = 1;
+            if (it < a.nticket) {
+                const InstDesc *d = a.inst + a.tickets[it];
+                skip = __hip_atomic_load(d->next_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= d->P;
+            }
+            sh_item = it;
+            sh_skip = skip;
+        }
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(sh_item);
+        const uint32_t skip = __builtin_amdgcn_readfirstlane(sh_skip);
+        __syncthreads();
+        if (item >= a.nticket) break;
+        if (skip) continue;
+        DescPtr D = descs + tickets[item];
+        if (D->place & PLACE_TABLES_LDS) coop_item<true, F>(a, D, smem, k0, k1);
+        else coop_item<false, F>(a, D, smem, k0, k1);
+    }
+}
+
 }  // namespace
 
 // Launch of the sampler for row format F.  The build compiles this file once
 // per format with MCPD_FMT set (the instantiations take most of the compile
 // time) and once without it for the dispatcher and the fill kernel.
 template <int F>
-int launch_sampler_fmt(const LaunchArgs &a, int grid, size_t lds, void *stream)
+int launch_sampler_fmt(const LaunchArgs &a, int grid, size_t lds, void *stream, bool coop)
 {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const void *fn = coop ? reinterpret_cast<const void *>(coop_kernel<F>)
+                          : reinterpret_cast<const void *>(sampler_kernel<F>);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(sampler_kernel<F>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return (int)e;
     }
-    hipLaunchKernelGGL((sampler_kernel<F>), dim3(grid), dim3(WG), lds, st, a);
+    if (coop) hipLaunchKernelGGL((coop_kernel<F>), dim3(grid), dim3(WG), lds, st, a);
+    else hipLaunchKernelGGL((sampler_kernel<F>), dim3(grid), dim3(WG), lds, st, a);
     return (int)hipGetLastError();
 }
 
-template int launch_sampler_fmt<MCPD_FMT>(const LaunchArgs &, int, size_t, void *);
+template int launch_sampler_fmt<MCPD_FMT>(const LaunchArgs &, int, size_t, void *, bool);
 
 #else
 
@@ -695,16 +1185,16 @@ __global__ void fill_zero_kernel(uint64_t *p, size_t n)
         p[i] = 0;
 }
 
-int launch_sampler(const LaunchArgs &a, int fmt, int grid, size_t lds, void *stream)
+int launch_sampler(const LaunchArgs &a, int fmt, int grid, size_t lds, void *stream, bool coop)
 {
     switch (fmt) {
-    case FMT_U8_4: return launch_sampler_fmt<FMT_U8_4>(a, grid, lds, stream);
-    case FMT_U8_5: return launch_sampler_fmt<FMT_U8_5>(a, grid, lds, stream);
-    case FMT_U8_8: return launch_sampler_fmt<FMT_U8_8>(a, grid, lds, stream);
-    case FMT_U8_12: return launch_sampler_fmt<FMT_U8_12>(a, grid, lds, stream);
-    case FMT_U16_4: return launch_sampler_fmt<FMT_U16_4>(a, grid, lds, stream);
-    case FMT_U16_8: return launch_sampler_fmt<FMT_U16_8>(a, grid, lds, stream);
-    case FMT_U16_12: return launch_sampler_fmt<FMT_U16_12>(a, grid, lds, stream);
+    case FMT_U8_4: return launch_sampler_fmt<FMT_U8_4>(a, grid, lds, stream, coop);
+    case FMT_U8_5: return launch_sampler_fmt<FMT_U8_5>(a, grid, lds, stream, coop);
+    case FMT_U8_8: return launch_sampler_fmt<FMT_U8_8>(a, grid, lds, stream, coop);
+    case FMT_U8_12: return launch_sampler_fmt<FMT_U8_12>(a, grid, lds, stream, coop);
+    case FMT_U16_4: return launch_sampler_fmt<FMT_U16_4>(a, grid, lds, stream, coop);
+    case FMT_U16_8: return launch_sampler_fmt<FMT_U16_8>(a, grid, lds, stream, coop);
+    case FMT_U16_12: return launch_sampler_fmt<FMT_U16_12>(a, grid, lds, stream, coop);
     default: return (int)hipErrorInvalidValue;
     }
 }

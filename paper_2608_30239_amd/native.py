@@ -44,7 +44,9 @@ class RunOpts(C.Structure):
         ("ticket_slots", C.c_uint32),
         ("use_graph", C.c_uint32),
         ("keep_slot_records", C.c_uint32),
+        ("narrow_lanes", C.c_uint32),
         ("bucket_rows", C.c_uint32),
+        ("kernel", C.c_uint32),
         ("slot_nstar", C.c_void_p),
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),
@@ -59,18 +61,22 @@ STAT_FIELDS = ("progress_units", "retained_units", "single_site_updates", "reps_
 
 class RunStats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [
-        ("placement", C.c_uint32), ("wg_per_cu", C.c_uint32), ("kernel_ms", C.c_double)]
+        ("placement", C.c_uint32), ("wg_per_cu", C.c_uint32), ("wg_slots", C.c_uint32),
+        ("kernel", C.c_uint32), ("kernel_ms", C.c_double)]
 
     def as_dict(self):
         d = {f: int(getattr(self, f)) for f in STAT_FIELDS}
         d["placement"] = int(self.placement)
         d["wg_per_cu"] = int(self.wg_per_cu)
+        d["wg_slots"] = int(self.wg_slots)
+        d["kernel"] = int(self.kernel)
         d["kernel_ms"] = float(self.kernel_ms)
         return d
 
 
 class TuneEntry(C.Structure):
-    _fields_ = [("wg_per_cu", C.c_uint32), ("ticket_slots", C.c_uint32), ("ms", C.c_double)]
+    _fields_ = [("wg_per_cu", C.c_uint32), ("ticket_slots", C.c_uint32), ("narrow_lanes", C.c_uint32),
+                ("kernel", C.c_uint32), ("ms", C.c_double)]
 
 
 # Every symbol include/mcpd.h declares.
@@ -123,7 +129,7 @@ def load(path: Optional[str] = None):
         L.mcpd_batch_create.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(RunOpts), vp, C.POINTER(vp)]
         L.mcpd_batch_run.argtypes = [vp, C.c_uint64, vp, vp, vp, vp]
         L.mcpd_batch_tune.argtypes = [vp, C.c_uint64, vp, C.c_uint32, vp]
-        L.mcpd_batch_config.argtypes = [vp, vp, vp, vp, vp]
+        L.mcpd_batch_config.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mcpd_batch_buckets.argtypes = [vp, C.c_int32, C.c_uint32, vp, vp]
         L.mcpd_batch_slot_records.argtypes = [vp, C.c_int32, vp, vp]
         L.mcpd_batch_destroy.argtypes = [vp]
@@ -287,15 +293,17 @@ class Batch:
         ent = (TuneEntry * cap)()
         cnt = C.c_uint32()
         _check(load().mcpd_batch_tune(self.h, seed, ent, cap, C.byref(cnt)), "mcpd_batch_tune")
-        return [dict(wg_per_cu=int(e.wg_per_cu), ticket_slots=int(e.ticket_slots), ms=float(e.ms))
+        return [dict(wg_per_cu=int(e.wg_per_cu), ticket_slots=int(e.ticket_slots),
+                     narrow_lanes=int(e.narrow_lanes), kernel=int(e.kernel), ms=float(e.ms))
                 for e in ent[:cnt.value]]
 
     def config(self):
         wg, ts, lanes = C.c_uint32(), C.c_uint32(), C.c_uint32()
         place = np.zeros(self.count, np.uint32)
-        _check(load().mcpd_batch_config(self.h, C.byref(wg), C.byref(ts), C.byref(lanes), _p(place)),
+        wl = np.zeros(self.count, np.uint32)
+        _check(load().mcpd_batch_config(self.h, C.byref(wg), C.byref(ts), C.byref(lanes), _p(place), _p(wl)),
                "mcpd_batch_config")
-        return dict(wg_per_cu=wg.value, ticket_slots=ts.value, lanes=lanes.value, placement=place)
+        return dict(wg_per_cu=wg.value, ticket_slots=ts.value, lanes=lanes.value, placement=place, wg_slots=wl)
 
     def buckets(self, i, rows):
         n = self.decoders[i].n

@@ -17,6 +17,13 @@ def _lib():
     N.load()
 
 
+# every generic case runs on both kernels: one slot per lane, and one slot
+# per wavefront with 64 speculative draws per step
+@pytest.fixture(params=[1, 2], ids=["lane", "coop"])
+def kern(request):
+    return request.param
+
+
 def compare(inst, budget, slots, k, m, seed=0, weights=None, tol=1e-12, **opt):
     """Run both sides and compare everything; returns (gpu, oracle)."""
     orc, nb = P.oracle_run(inst, budget, slots, k, m, seed, weights=weights, **opt)
@@ -33,80 +40,104 @@ def compare(inst, budget, slots, k, m, seed=0, weights=None, tol=1e-12, **opt):
     return gpu, orc
 
 
-def test_tiny_plain_one_pair_per_slot():
+def test_tiny_plain_one_pair_per_slot(kern):
     inst, rp = I.tiny_plain()
-    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed)
+    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed, kernel=kern)
+    assert gpu["stats"]["kernel"] == kern
     assert gpu["stats"]["reps_retained"] == rp.slots
 
 
 @pytest.mark.parametrize("slots,mult,k,m", [(1000, 2.5, 10, 50), (333, 4.0, 0, 0), (257, 3.3, 7, 7),
                                             (64, 9.0, 0, 20), (1, 5.0, 3, 30)])
-def test_tiny_refill_ragged(slots, mult, k, m):
+def test_tiny_refill_ragged(slots, mult, k, m, kern):
     inst, _ = I.tiny_plain()
     B = int(mult * max(m, 1))
-    gpu, orc = compare(inst, B * slots, slots, k, m, seed=3, hist_width=1)
+    gpu, orc = compare(inst, B * slots, slots, k, m, seed=3, hist_width=1, kernel=kern)
     if mult > 1:
         assert gpu["stats"]["reps_retained"] > slots
 
 
-def test_refill_off_and_instance_id():
+def test_refill_off_and_instance_id(kern):
     inst, _ = I.tiny_plain()
-    compare(inst, 4096 * 200, 4096, 10, 50, seed=5, refill=0, instance_id=77)
+    compare(inst, 4096 * 200, 4096, 10, 50, seed=5, refill=0, instance_id=77, kernel=kern)
 
 
-def test_meeting_cap_truncation():
+def test_meeting_cap_truncation(kern):
     inst = I.make_instance("noisy12", 12, 6, 3, 2, 0.25, 0.25, prior=0.3, seed=3)
-    gpu, orc = compare(inst, 2000 * 30, 2000, 2, 6, seed=9, max_steps=8, hist_width=1)
+    gpu, orc = compare(inst, 2000 * 30, 2000, 2, 6, seed=9, max_steps=8, hist_width=1, kernel=kern)
     assert orc["stats"]["cap_hits"] > 0
 
 
-def test_low_bit_refinement_path():
+def test_low_bit_refinement_path(kern):
     # u_hi_bits = 2 makes the high part of U tie with the threshold often,
     # so the low-bit block decides many draws
     inst, _ = I.tiny_plain()
-    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=2)
-    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=13)
+    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=2, kernel=kern)
+    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=13, kernel=kern)
 
 
-def test_user_weights():
+def test_user_weights(kern):
     inst, _ = I.tiny_plain()
     w = np.linspace(1.0, 3.0, inst.n)
-    compare(inst, 2048 * 120, 2048, 10, 50, seed=4, weights=w)
+    compare(inst, 2048 * 120, 2048, 10, 50, seed=4, weights=w, kernel=kern)
 
 
-def test_degree_up_to_twelve_and_wide_pools():
+def test_degree_up_to_twelve_and_wide_pools(kern):
     inst = I.make_instance("deg12", 300, 200, (6, 12), 4, 0.08, 0.12, prior=4 / 300, seed=7)
     k, m = I.window_for_sweeps(1, inst.n)
-    compare(inst, 1024 * 4 * m, 1024, k, m, seed=1)
+    compare(inst, 1024 * 4 * m, 1024, k, m, seed=1, kernel=kern)
 
 
 def test_global_state_path():
-    # too large for LDS even at 64 lanes per workgroup
+    # chain state and tables in global memory (forced)
     inst = I.make_instance("big", 12000, 900, (3, 7), 6, 0.1, 0.1, prior=6 / 12000, seed=2)
     k, m = 10, 200
-    gpu, _ = compare(inst, 512 * 700, 512, k, m, seed=6)
-    assert gpu["stats"]["placement"] == 0
+    gpu, _ = compare(inst, 512 * 700, 512, k, m, seed=6, plan=4)
+    assert gpu["stats"]["placement"] == 0 and gpu["stats"]["wg_slots"] == 256 and gpu["stats"]["kernel"] == 1
+
+
+def test_narrow_lds_layout():
+    # 4.8 KB of state per lane: by default a workgroup runs 33 lanes with the
+    # state in LDS; the same run with wide layouts only keeps it in global memory
+    inst = I.make_instance("big", 12000, 900, (3, 7), 6, 0.1, 0.1, prior=6 / 12000, seed=2)
+    gpu, _ = compare(inst, 512 * 700, 512, 10, 200, seed=6, kernel=1)
+    assert gpu["stats"]["placement"] == 1 and 8 <= gpu["stats"]["wg_slots"] < 256
+    gpu2, _ = compare(inst, 512 * 700, 512, 10, 200, seed=6, narrow_lanes=256, kernel=1)
+    assert gpu2["stats"]["placement"] in (0, 2) and gpu2["stats"]["wg_slots"] == 256
+    gpu3, _ = compare(inst, 512 * 700, 512, 10, 200, seed=6, kernel=2)
+    assert gpu3["stats"]["placement"] & 5 == 5 and gpu3["stats"]["wg_slots"] == 4
 
 
 def test_lds_state_global_tables():
     # state fills LDS at 256 lanes, the tables no longer fit beside it
     inst = I.make_instance("lds_state_only", 1600, 110, 5, 3, 0.05, 0.1, prior=3 / 1600, seed=4)
-    gpu, _ = compare(inst, 2048 * 2000, 2048, 60, 600, seed=2)
+    gpu, _ = compare(inst, 2048 * 2000, 2048, 60, 600, seed=2, kernel=1)
     assert gpu["stats"]["placement"] == 1
 
 
 def test_global_state_lds_tables():
     inst = I.make_instance("lds_tables_only", 3000, 400, (3, 7), 5, 0.1, 0.05, prior=5 / 3000, seed=5)
-    gpu, _ = compare(inst, 1024 * 1500, 1024, 30, 500, seed=3)
+    gpu, _ = compare(inst, 1024 * 1500, 1024, 30, 500, seed=3, plan=3, kernel=1)
     assert gpu["stats"]["placement"] == 2
 
 
-def test_deterministic_repeat():
+def test_narrow_layout_with_tables_and_ragged_lanes():
+    # state 1.5 KB per lane: narrow layouts with and without the tables
+    inst = I.make_instance("lds_tables_only", 3000, 400, (3, 7), 5, 0.1, 0.05, prior=5 / 3000, seed=5)
+    gpu, _ = compare(inst, 1000 * 1500, 1000, 30, 500, seed=4, kernel=1)
+    assert gpu["stats"]["placement"] & 1 and gpu["stats"]["wg_slots"] < 256
+    gpu, _ = compare(inst, 1000 * 1500, 1000, 30, 500, seed=4, plan=1, narrow_lanes=8, kernel=1)
+    assert gpu["stats"]["placement"] == 3 and gpu["stats"]["wg_slots"] < 256
+    gpu, _ = compare(inst, 1000 * 1500, 1000, 30, 500, seed=4, plan=2, kernel=2)
+    assert gpu["stats"]["placement"] == 5
+
+
+def test_deterministic_repeat(kern):
     inst, rp = I.tiny_plain()
     dec = N.Decoder(inst)
     try:
-        a = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3)
-        b = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3)
+        a = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3, kernel=kern)
+        b = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3, kernel=kern)
     finally:
         dec.close()
     assert np.array_equal(a["marginals"], b["marginals"])
@@ -130,8 +161,8 @@ def test_invalid_arguments_raise():
         dec.close()
 
 
-def test_paper_shaped_full_size():
+def test_paper_shaped_full_size(kern):
     inst, rp = I.paper_shaped()
-    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed)
-    assert gpu["stats"]["placement"] == 3      # state and tables in LDS
+    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed, kernel=kern)
+    assert gpu["stats"]["placement"] & 3 == 3      # state and tables in LDS
     assert gpu["stats"]["nstar_max"] >= 3
