@@ -8,6 +8,12 @@ resident in device memory before the timed region; every step runs the
 sampler kernel, the integer bucket reduction and the final FP64 division,
 with a new seed per step.
 
+Also reported on the same line: the two batched workloads (128-instance
+noise sweep, 256-instance uneven batch) as one persistent launch replayed
+from a captured graph, and the learned selection weights against the score
+weights on the same paper-shaped workload at equal budget (RMSE against an
+independent long reference run, device seconds, efficiency 1/(MSE s)).
+
 Prints one JSON line.  Only one GPU is used; --gpus N > 1 exits.
 """
 
@@ -62,17 +68,69 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(inst, rp, threads: int, slots: int):
+def cpu_baseline(inst, rp, threads: int, min_seconds: float = 10.0, max_runs: int = 12):
+    """The oracle on the same workload, whole runs with new seeds until at
+    least min_seconds of CPU time have passed."""
     from oracle import oracle as O
     M = O.Model(inst)
-    B = rp.budget // rp.slots
-    t0 = time.perf_counter()
-    r = M.run(B * slots, slots, rp.k, rp.m, seed=rp.seed, nthreads=threads)
-    dt = time.perf_counter() - t0
-    units = r["stats"]["retained_units"] + r["stats"]["discarded_units"]
+    units, dt, runs = 0, 0.0, 0
+    while runs < max_runs and (runs == 0 or dt < min_seconds):
+        t0 = time.perf_counter()
+        r = M.run(rp.budget, rp.slots, rp.k, rp.m, seed=rp.seed + runs, nthreads=threads)
+        dt += time.perf_counter() - t0
+        units += r["stats"]["retained_units"] + r["stats"]["discarded_units"]
+        runs += 1
     return dict(value=units / dt, unit="coupled Gibbs updates/s", cores=threads, kind="oracle",
-                sample=f"{slots} of the {rp.slots} slots of the same workload (B={B}); "
+                sample=f"{runs} whole runs of the workload ({rp.slots} slots, budget {rp.budget}); "
                        f"{units} coupled updates in {dt:.2f} s")
+
+
+def batch_lines(steps: int):
+    """One persistent launch per batched workload, replayed from its graph."""
+    from paper_2608_30239_amd import instances as I
+    from paper_2608_30239_amd import native as N
+    out = {}
+    insts, rp = I.noise_sweep()
+    work = {"noise_sweep_128x1298": (insts, [(rp.budget, rp.slots, rp.k, rp.m)] * len(insts))}
+    insts, params = I.uneven_batch()
+    work["uneven_256"] = (insts, [(p.budget, p.slots, p.k, p.m) for p in params])
+    for name, (insts, params) in work.items():
+        decs = [N.Decoder(x) for x in insts]
+        bt = N.Batch(decs, params)
+        try:
+            bt.run(12345, outputs=False)
+            ms, units = [], 0
+            for s in range(steps):
+                r = bt.run(s, outputs=False)
+                ms.append(r[0]["stats"]["kernel_ms"])
+                units += sum(x["stats"]["progress_units"] for x in r)
+            cfg = bt.config()
+            out[name] = dict(instances=len(insts), graph_ms=sum(ms) / len(ms),
+                             updates_per_s=units / (sum(ms) / 1e3), kernel=r[0]["stats"]["kernel"],
+                             wg_per_cu=cfg["wg_per_cu"], ticket_slots=cfg["ticket_slots"],
+                             tau_max=max(x["stats"]["tau_max"] for x in r))
+        finally:
+            bt.close()
+            for d in decs:
+                d.close()
+    return out
+
+
+def learned_line(nref: int, nrep: int):
+    """Learned against score weights on the paper-shaped workload."""
+    from paper_2608_30239_amd import instances as I
+    from paper_2608_30239_amd import native as N
+    from paper_2608_30239_amd import selection as S
+    params, rep = S.load_trained()
+    net = N.Mlp(params)
+    try:
+        res = S.evaluate(net, nref=nref, nrep=nrep, instances=[I.paper_shaped()], log=lambda m: None)
+    finally:
+        net.close()
+    row = res["rows"][0]
+    keep = ("rmse_score", "rmse_learned", "seconds_score", "seconds_learned", "gain", "var_gain")
+    return dict({k: row[k] for k in keep}, reference_runs=nref, runs=nrep,
+                metric="efficiency 1/(MSE x device seconds), learned over score weights")
 
 
 def copy_calibration(mib: int, reps: int):
@@ -93,7 +151,8 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slots", type=int, default=16384)
+    ap.add_argument("--no-batches", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -121,6 +180,8 @@ def main():
         kernel_ms.append(r["stats"]["kernel_ms"])
     dt = time.perf_counter() - t0
     dec.close()
+    kernel_name = {1: "sampler_kernel (one slot per lane)",
+                   2: "coop_kernel (one slot per wavefront, 64 speculative draws per step)"}[r["stats"]["kernel"]]
 
     value = units / dt
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
@@ -133,13 +194,13 @@ def main():
         "unit": "Tops/s",
         "frac": achieved_ops / ALU_PEAK_OPS,
         "traffic": measured_traffic(),
-        "kernel": "mcpd sampler_kernel (state and tables in LDS, 5-entry rows)",
+        "kernel": kernel_name + ", chain state and tables in LDS, 5-entry rows",
         "alg_ops_per_update": alg_ops_per_update(d_mean),
         "lds_bytes_per_update": lds_bytes_per_update(d_mean),
         "lds_achieved_TBps": lds_bytes_per_update(d_mean) * units_per_launch / avg_kernel_s / 1e12,
     }
     out = {
-        "metric": "coupled Gibbs updates/s",
+        "metric": "coupled Gibbs updates/s + marginal RMSE per GPU-second (learned vs score weights)",
         "value": value,
         "unit": "coupled Gibbs updates/s",
         "n_gpus": 1,
@@ -158,9 +219,13 @@ def main():
         "kernel_updates_per_s": units_per_launch / avg_kernel_s,
         "roofline": roofline,
     }
+    if not args.no_batches:
+        out["batches"] = batch_lines(3)
+    if not args.no_learned:
+        out["learned_vs_score"] = learned_line(16, 8)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(inst, rp, threads, args.cpu_slots)
+        out["cpu_baseline"] = cpu_baseline(inst, rp, threads)
     print(json.dumps(out), flush=True)
 
 
