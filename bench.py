@@ -86,7 +86,8 @@ def cpu_baseline(inst, rp, threads: int, min_seconds: float = 10.0, max_runs: in
 
 
 def batch_lines(steps: int):
-    """One persistent launch per batched workload, replayed from its graph."""
+    """One persistent launch per batched workload, autotuned, then replayed
+    from its captured graph."""
     from paper_2608_30239_amd import instances as I
     from paper_2608_30239_amd import native as N
     out = {}
@@ -98,6 +99,7 @@ def batch_lines(steps: int):
         decs = [N.Decoder(x) for x in insts]
         bt = N.Batch(decs, params)
         try:
+            tuned = bt.tune(12345)
             bt.run(12345, outputs=False)
             ms, units = [], 0
             for s in range(steps):
@@ -107,7 +109,8 @@ def batch_lines(steps: int):
             cfg = bt.config()
             out[name] = dict(instances=len(insts), graph_ms=sum(ms) / len(ms),
                              updates_per_s=units / (sum(ms) / 1e3), kernel=r[0]["stats"]["kernel"],
-                             wg_per_cu=cfg["wg_per_cu"], ticket_slots=cfg["ticket_slots"],
+                             group_lanes=r[0]["stats"]["group_lanes"], wg_per_cu=cfg["wg_per_cu"],
+                             ticket_slots=cfg["ticket_slots"], tuner_candidates=len(tuned),
                              tau_max=max(x["stats"]["tau_max"] for x in r))
         finally:
             bt.close()
@@ -181,7 +184,8 @@ def main():
     dt = time.perf_counter() - t0
     dec.close()
     kernel_name = {1: "sampler_kernel (one slot per lane)",
-                   2: "coop_kernel (one slot per wavefront, 64 speculative draws per step)"}[r["stats"]["kernel"]]
+                   2: f"coop_kernel (one slot per {r['stats']['group_lanes']} lanes drawing speculatively)"}[
+        r["stats"]["kernel"]]
 
     value = units / dt
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3

@@ -86,9 +86,12 @@ typedef struct mcpd_run_opts {
     uint32_t kernel;        /* 0 = auto: the cooperative kernel when every
                                instance's chain states fit it, else the lane
                                kernel; 1 = lane kernel (one slot per lane);
-                               2 = cooperative kernel (one slot per wavefront,
-                               64 speculative draws per step), MCPD_EINVAL if
-                               the states do not fit                          */
+                               2 = cooperative kernel (one slot per group of
+                               lanes, one speculative draw per lane and step),
+                               MCPD_EINVAL if the states do not fit           */
+    uint32_t group_lanes;   /* cooperative kernel: lanes per slot, 8, 16, 32 or
+                               64 (0 = default 16)                            */
+    uint32_t reserved;
     /* Optional host outputs of mcpd_run_unbiased (NULL = not wanted; must be
        NULL for batches). */
     uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */
@@ -123,8 +126,11 @@ typedef struct mcpd_run_stats {
     uint32_t wg_per_cu;           /* workgroups per CU of the launch            */
     uint32_t wg_slots;            /* slots a workgroup runs at once for this
                                      instance: 256 lanes (fewer in a narrow
-                                     layout) or 4 wavefronts (cooperative)     */
+                                     layout), or 256 / group_lanes groups
+                                     (cooperative)                              */
     uint32_t kernel;              /* 1 = lane kernel, 2 = cooperative kernel    */
+    uint32_t group_lanes;         /* lanes per slot (1 for the lane kernel)     */
+    uint32_t reserved;
     double kernel_ms;             /* device time: the sampler launch, or for a
                                      batch replayed as a graph the whole replay
                                      (key copy, zeroing, sampler, copy back)   */
@@ -137,6 +143,8 @@ typedef struct mcpd_tune_entry {
     uint32_t narrow_lanes;        /* least lanes of a narrow LDS layout (0 = wide
                                      layouts only)                              */
     uint32_t kernel;              /* 1 = lane kernel, 2 = cooperative kernel    */
+    uint32_t group_lanes;         /* lanes per slot (1 for the lane kernel)     */
+    uint32_t reserved;
     double ms;                    /* sampler time of one full run               */
 } mcpd_tune_entry;
 
@@ -237,7 +245,8 @@ int mcpd_batch_run(mcpd_batch *batch, uint64_t seed, double *const *marginals,
  * values), time the sampler, keep the fastest.  Lane kernel layouts: wide
  * only (chain state in LDS for 256 lanes when it fits, else in global
  * memory), or also narrow (a workgroup runs only as many lanes as fit the
- * state in LDS, at least 8); cooperative kernel: one state per wavefront.
+ * state in LDS, at least 8); cooperative kernel: one state per group of 8,
+ * 16, 32 or 64 lanes.
  * The results do not depend on the shape.  entries: host [cap] or NULL;
  * count receives the number of candidates measured. */
 int mcpd_batch_tune(mcpd_batch *batch, uint64_t seed, mcpd_tune_entry *entries, uint32_t cap,

@@ -39,7 +39,7 @@ constexpr uint32_t WG_LANES = 256;
 
 enum Place : uint32_t { PLACE_STATE_LDS = 1, PLACE_TABLES_LDS = 2, PLACE_COOP = 4 };
 
-// Wavefronts of a workgroup of the cooperative kernel (one slot each).
+// Wavefronts of a workgroup of the cooperative kernel.
 constexpr uint32_t COOP_WAVES_PER_WG = WG_LANES / 64;
 
 // One instance of a launch, in device memory.  The kernel reads it with
@@ -70,7 +70,7 @@ struct InstDesc {
     // Placement in the launch's dynamic LDS (dword offsets).
     uint32_t place;         // Place bits
     uint32_t lds_hist, lds_tab;
-    uint32_t lds_state, wave_words;   // cooperative kernel: first wave's state, words per wave
+    uint32_t lds_state, wave_words;   // cooperative kernel: first group's state, words per group
     uint32_t tab_off_thr, tab_off_alias, tab_off_rows, tab_bytes;   // within the table block (bytes)
     // Outputs (zeroed before the launch).
     int64_t *S1;            // [nbuckets * n]
@@ -93,7 +93,7 @@ struct LaunchArgs {
     uint32_t list_cap;          // touched-list capacity per lane
     uint32_t acc_stride;        // >= every n
     uint32_t gwords;            // >= every global-state instance's words_bits + words_cnt
-    uint32_t pad;
+    uint32_t group_log2;        // cooperative kernel: log2 of the lanes that run one slot (3..6)
     const uint64_t *seed;       // device copy of the 64-bit key
     int64_t *acc;               // [lanes * acc_stride] spilled numerators (kept zero between slots)
     uint32_t *lists;            // [lanes * list_cap]

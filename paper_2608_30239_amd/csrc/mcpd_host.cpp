@@ -278,12 +278,13 @@ struct Config {
     uint32_t wg_per_cu = 1;   // workgroups of 256 lanes per compute unit
     uint32_t spl = 1;         // slots per lane (or per wavefront) one ticket stands for
     uint32_t narrow = 8;      // least lanes of a narrow LDS layout (0 = none)
-    bool coop = false;        // the cooperative kernel (one slot per wavefront)
+    bool coop = false;        // the cooperative kernel (one slot per group of lanes)
+    uint32_t group_log2 = 4;  // its lanes per slot: 2^group_log2 (3..6)
 };
 
-// Most workgroups of the cooperative kernel per CU (its registers allow 7
+// Most workgroups of the cooperative kernel per CU (its registers allow 5
 // wavefronts per SIMD).
-constexpr uint32_t COOP_MAX_WG = 7;
+constexpr uint32_t COOP_MAX_WG = 5;
 
 // Placement of one instance in a workgroup's LDS of `budget` bytes.
 struct Layout {
@@ -355,18 +356,20 @@ int layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, u
 // Placement for the cooperative kernel: the histogram, the tables when they
 // fit, and one chain state per wavefront (words rounded to 16 bytes).
 // Returns false when the wavefronts' states do not fit.
-bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan, Layout &L)
+bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan,
+                 uint32_t group_log2, Layout &L)
 {
     if (layout(I, fmt, hist_bins, budget, 4, 0, L)) return false;   // fills the sizes
     const size_t words = (size_t)L.words_bits + L.words_cnt;
     const size_t ww = (words + 3) & ~(size_t)3;
-    const size_t states = ww * COOP_WAVES_PER_WG * 4;
+    const size_t groups = (size_t)COOP_WAVES_PER_WG * (64u >> group_log2);
+    const size_t states = ww * groups * 4;
     const size_t hist = align16((size_t)hist_bins * 4u);
     if (plan == 3 || plan == 4) return false;   // plans that keep the state out of LDS
     const bool tl = (plan == 0 || plan == 1) && hist + L.tab_bytes + states <= budget;
     if (plan == 1 && !tl) return false;
     if (hist + states > budget) return false;
-    L.lanes = COOP_WAVES_PER_WG;
+    L.lanes = (uint32_t)groups;
     L.place = PLACE_STATE_LDS | PLACE_COOP | (tl ? PLACE_TABLES_LDS : 0u);
     L.lds_hist = 0;
     L.lds_tab = (uint32_t)(hist / 4);
@@ -456,6 +459,8 @@ int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool bat
     if (o.wg_per_cu > 8) return fail(MCPD_EINVAL, "wg_per_cu must be 0..8");
     if (o.narrow_lanes > WG_LANES) return fail(MCPD_EINVAL, "narrow_lanes must be 0..256");
     if (o.kernel > 2) return fail(MCPD_EINVAL, "kernel must be 0 (auto), 1 (lane) or 2 (cooperative)");
+    if (o.group_lanes && o.group_lanes != 8 && o.group_lanes != 16 && o.group_lanes != 32 && o.group_lanes != 64)
+        return fail(MCPD_EINVAL, "group_lanes must be 0, 8, 16, 32 or 64");
     const uint64_t last_id = (uint64_t)o.instance_id + (batch_ids ? items.size() - 1 : 0);
     if (last_id >= (1u << 24)) return fail(MCPD_EINVAL, "instance ids must be < 2^24");
     for (const Item &it : items) {
@@ -472,6 +477,17 @@ int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool bat
     return MCPD_OK;
 }
 
+// Lanes per slot of the cooperative kernel from the options (default 16).
+uint32_t group_log2_of(const mcpd_run_opts &o)
+{
+    uint32_t lg = 4;
+    if (o.group_lanes) {
+        lg = 3;
+        while ((1u << lg) < o.group_lanes) ++lg;
+    }
+    return lg;
+}
+
 // Least lanes of a narrow layout from the options (0 = none).
 uint32_t narrow_of(const mcpd_run_opts &o)
 {
@@ -481,14 +497,17 @@ uint32_t narrow_of(const mcpd_run_opts &o)
 
 // Workgroups per CU at which every instance fits the cooperative layout
 // (0 if none).
-uint32_t coop_wg(const Launch &L, uint32_t most)
+uint32_t coop_wg(const Launch &L, uint32_t most, uint32_t group_log2)
 {
     for (uint32_t wg = most; wg >= 1; --wg) {
         const size_t budget = (LDS_BYTES / wg - 1024) & ~(size_t)1023;
         bool all = true;
         for (const Item &it : L.items) {
             Layout lay;
-            if (!coop_layout(it.I, L.fmt, L.opts.hist_bins, budget, L.opts.plan, lay)) { all = false; break; }
+            if (!coop_layout(it.I, L.fmt, L.opts.hist_bins, budget, L.opts.plan, group_log2, lay)) {
+                all = false;
+                break;
+            }
         }
         if (all) return wg;
     }
@@ -505,9 +524,11 @@ Config default_config(const Launch &L)
     Config c;
     c.narrow = narrow_of(L.opts);
     const uint32_t kernel = L.opts.kernel;
-    const uint32_t cw = kernel == 1 ? 0u : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : COOP_MAX_WG);
+    const uint32_t lg = group_log2_of(L.opts);
+    const uint32_t cw = kernel == 1 ? 0u : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : COOP_MAX_WG, lg);
     if (cw) {
         c.coop = true;
+        c.group_log2 = lg;
         c.wg_per_cu = cw;
         c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 4u;
         return c;
@@ -549,7 +570,7 @@ int plan(Launch &L, const Config &c)
         mcpd_instance *I = it.I;
         Layout lay;
         if (c.coop) {
-            if (!coop_layout(I, L.fmt, o.hist_bins, budget, o.plan, lay))
+            if (!coop_layout(I, L.fmt, o.hist_bins, budget, o.plan, c.group_log2, lay))
                 return fail(MCPD_EINVAL, "an instance's chain states do not fit the cooperative layout");
         } else {
             int rc = layout(I, L.fmt, o.hist_bins, budget, o.plan, c.narrow, lay);
@@ -683,6 +704,7 @@ LaunchArgs launch_args(const Launch &L)
     a.list_cap = L.list_cap;
     a.acc_stride = L.acc_stride;
     a.gwords = L.gwords;
+    a.group_log2 = L.cfg.group_log2;
     a.seed = L.d_seed;
     a.acc = L.d_acc;
     a.lists = L.d_lists;
@@ -804,6 +826,7 @@ int finish_item(const Launch &L, size_t i, double *marginals, double *stderr_out
         stats->wg_per_cu = L.cfg.wg_per_cu;
         stats->wg_slots = d.lanes;
         stats->kernel = L.coop ? 2u : 1u;
+        stats->group_lanes = L.coop ? 1u << L.cfg.group_log2 : 1u;
         stats->kernel_ms = L.last_ms;
     }
     if (L.opts.strict_cap && st[ST_CAP_HITS]) return fail(MCPD_ECAP, "a retained pair hit the meeting cap");
@@ -1143,20 +1166,17 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
         }
     }
     if (L.opts.kernel != 1) {
-        const uint32_t top = coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : COOP_MAX_WG);
-        if (top) {
-            const uint32_t wgs[] = {top, (top + 1) / 2};
-            const uint32_t spls[] = {2, 8};
-            for (int wi = 0; wi < (top > 1 ? 2 : 1); ++wi) {
-                for (uint32_t sp : spls) {
-                    if (L.opts.ticket_slots && sp != L.opts.ticket_slots) continue;
-                    Config c;
-                    c.coop = true;
-                    c.wg_per_cu = wgs[wi];
-                    c.spl = sp;
-                    cands.push_back(c);
-                }
-            }
+        const uint32_t lgs[] = {3, 4, 5, 6};
+        for (uint32_t lg : lgs) {
+            if (L.opts.group_lanes && lg != group_log2_of(L.opts)) continue;
+            const uint32_t top = coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : COOP_MAX_WG, lg);
+            if (!top) continue;
+            Config c;
+            c.coop = true;
+            c.group_log2 = lg;
+            c.wg_per_cu = top;
+            c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 4u;
+            cands.push_back(c);
         }
     }
     Config best = L.cfg;
@@ -1168,7 +1188,8 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
         if (rc) return rc;
         if ((rc = execute(L, seed, false))) return rc;
         const double ms = L.last_ms;
-        if (entries && done < cap) entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, c.narrow, c.coop ? 2u : 1u, ms};
+        if (entries && done < cap)
+            entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, c.narrow, c.coop ? 2u : 1u, c.coop ? 1u << c.group_log2 : 1u, 0u, ms};
         ++done;
         if (ms < best_ms) { best_ms = ms; best = c; }
     }

@@ -701,20 +701,22 @@ __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
 }
 
 // ------------------------------------------------------------ cooperative
-// One wavefront runs one slot at a time.  Each iteration the 64 lanes draw
-// the next 64 updates of the same pair speculatively against the current
-// state; a ballot finds the first lane whose update changes either chain.
-// Every lane before it changed nothing, so their updates were made on the
-// exact state and stand; the first changing lane's update stands too and is
-// applied; the lanes after it are dropped and redrawn in the next iteration.
-// The committed draws and decisions are exactly those of the one-lane
-// sampler.  The chain state of a slot (0.5 KB for 1298 clones and 97 pools)
-// is small enough that every wave of a CU keeps its own in LDS, and a slot
-// whose pair takes very long to meet advances tens of draws per iteration.
+// A group of GL lanes (8, 16, 32 or 64: a wavefront holds 64 / GL groups)
+// runs one slot at a time.  Each step the group's lanes draw the next GL
+// updates of the pair speculatively against the current state; a ballot
+// finds the first lane whose update changes either chain.  Every lane before
+// it changed nothing, so their updates were made on the exact state and
+// stand; the first changing lane's update stands too and is applied; the
+// lanes after it are dropped and redrawn in the next step.  The committed
+// draws and decisions are exactly those of the one-lane sampler.  A slot's
+// chain state (0.5 KB for 1298 clones and 97 pools) is small enough that
+// every group keeps its own in LDS, and a pair that takes very long to meet
+// advances many draws per step.  Smaller groups waste fewer speculative
+// draws when changes are frequent; larger ones go further when they are rare.
 constexpr uint32_t COOP_WAVES = WG / 64;   // wavefronts per workgroup
 
-struct WaveSlot {
-    uint32_t p, r, t, nret, tau, target, lim, lc, f0, f1;
+struct GroupSlot {
+    uint32_t mode, p, r, t, nret, tau, target, lim, lc, f0, f1;
     int32_t mu, sgn;
     uint64_t S;
 };
@@ -724,24 +726,27 @@ struct Coop {
     const LaunchArgs &a;
     DescPtr D;
     uint32_t k0, k1;
-    uint32_t *st;           // this wave's bit words (LDS)
+    uint32_t *st;           // this group's bit words (LDS)
     uint32_t *cst;          // its count words
     const uint64_t *thr;
     const uint32_t *alias;
     const uint32_t *rows;
-    uint32_t lane;          // lane within the wave
-    int64_t *acc;           // this wave's numerator row
+    uint32_t gl;            // lane within the group
+    uint32_t gsz;           // lanes per group
+    uint32_t leader;        // the group's first lane in the wavefront
+    uint64_t gmask;         // the group's lanes in a wavefront ballot
+    int64_t *acc;           // this group's numerator row
     uint32_t *list;         // its touched list
     uint32_t *hist_lds;
-    uint64_t *ls;           // this wave's statistics (global, written by lane 0)
+    uint64_t *ls;           // its statistics (global, written by the leader)
 
     __device__ __forceinline__ void stat_add(int i, uint64_t v) const
     {
-        if (lane == 0) __hip_atomic_fetch_add(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (gl == 0) __hip_atomic_fetch_add(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __device__ __forceinline__ void stat_max(int i, uint64_t v) const
     {
-        if (lane == 0) __hip_atomic_fetch_max(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (gl == 0) __hip_atomic_fetch_max(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
     __device__ __forceinline__ uint32_t site(uint32_t sw) const
@@ -753,7 +758,7 @@ struct Coop {
         return (sw & kmask) < (aw & kmask) ? col : (aw >> cb);
     }
 
-    __device__ __forceinline__ uint64_t low_bits(const WaveSlot &s, uint32_t t) const
+    __device__ __forceinline__ uint64_t low_bits(const GroupSlot &s, uint32_t t) const
     {
         uint32_t o[4];
         philox10(t, s.r, s.p, D->g | (1u << 24), k0, k1, o);
@@ -761,8 +766,8 @@ struct Coop {
         return v >> (11u + a.ubits);
     }
 
-    __device__ __forceinline__ uint32_t decide(const WaveSlot &s, uint32_t t, uint32_t hw, uint64_t T, bool &have_lo,
-                                               uint64_t &lo) const
+    __device__ __forceinline__ uint32_t decide(const GroupSlot &s, uint32_t t, uint32_t hw, uint64_t T,
+                                               bool &have_lo, uint64_t &lo) const
     {
         const uint32_t b = a.ubits;
         const uint32_t hb = hw >> (32u - b);
@@ -772,7 +777,7 @@ struct Coop {
         return lo <= (T & ((1ull << (53u - b)) - 1ull)) ? 1u : 0u;
     }
 
-    __device__ __forceinline__ void wave_fence() const
+    __device__ __forceinline__ void lds_fence() const
     {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -782,12 +787,10 @@ struct Coop {
     __device__ __forceinline__ void reset_state() const
     {
         const uint32_t nw = D->words_bits + D->words_cnt;
-        for (uint32_t w = lane; w < nw; w += 64u) st[w] = 0u;
-        wave_fence();
+        for (uint32_t w = gl; w < nw; w += gsz) st[w] = 0u;
+        lds_fence();
     }
 
-    // The numerator of clone j (wave-wide add from one lane), recorded in the
-    // touched list by the caller.
     __device__ __forceinline__ void add(uint32_t j, uint64_t v) const
     {
         __hip_atomic_fetch_add(reinterpret_cast<uint64_t *>(acc + j), v, __ATOMIC_RELAXED,
@@ -811,14 +814,15 @@ struct Coop {
         if (hi) atomicAdd(q + 2, (unsigned long long)hi);
     }
 
-    // Boundary term G(C) Delta_j(C) of a pair stopped by the cap, lanes over
-    // the bit words; the touched list is given up (the flush scans the row).
-    __device__ void truncation(WaveSlot &s) const
+    // Boundary term G(C) Delta_j(C) of a pair stopped by the cap, the group's
+    // lanes over the bit words; the touched list is given up (the flush scans
+    // the row).
+    __device__ void truncation(GroupSlot &s) const
     {
         const uint32_t C = s.t;
         if (C < D->k + 1u) return;
         const uint64_t G = gsum(C, D->k, D->ell, D->W);
-        for (uint32_t w = lane; w < D->words_bits; w += 64u) {
+        for (uint32_t w = gl; w < D->words_bits; w += gsz) {
             const uint32_t word = st[w];
             uint32_t mis = (word ^ (word >> 1)) & 0x55555555u;
             while (mis) {
@@ -831,12 +835,12 @@ struct Coop {
         s.lc = a.list_cap + 1u;
     }
 
-    __device__ void flush_slot(WaveSlot &s) const
+    __device__ void flush_slot(GroupSlot &s) const
     {
         const uint32_t nstar = s.nret;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         if (s.lc <= a.list_cap) {
-            for (uint32_t e = lane; e < s.lc; e += 64u) {
+            for (uint32_t e = gl; e < s.lc; e += gsz) {
                 const uint32_t j = __hip_atomic_load(list + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -844,31 +848,33 @@ struct Coop {
             }
         } else {
             stat_add(ST_LIST_OVERFLOWS, 1);
-            for (uint32_t j = lane; j < (uint32_t)D->n; j += 64u) {
+            for (uint32_t j = gl; j < (uint32_t)D->n; j += gsz) {
                 const int64_t v = (int64_t)__hip_atomic_exchange(reinterpret_cast<uint64_t *>(acc + j), (uint64_t)0,
                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (v != 0) emit(nstar, j, v);
             }
         }
-        if (lane == 0) {
+        if (gl == 0) {
             if (D->slot_nstar) D->slot_nstar[s.p] = nstar;
             if (D->slot_units) D->slot_units[s.p] = s.S;
         }
         stat_max(ST_NSTAR_MAX, nstar);
+        s.mode = MODE_NEED_SLOT;
     }
 
-    __device__ __forceinline__ void begin_rollback(WaveSlot &s, uint32_t draws) const
+    __device__ __forceinline__ void begin_rollback(GroupSlot &s, uint32_t draws) const
     {
         stat_add(ST_REPS_ABORTED, 1);
         stat_add(ST_ROLLBACK_UNITS, draws);
         stat_add(ST_PROGRESS, 2ull * draws);
         s.target = draws;
         s.sgn = -1;
+        s.mode = MODE_NEED_REP;
     }
 
-    // After the draw count reached the replication's limit: 0 = keep going,
-    // 1 = next replication (or replay), 2 = slot finished.
-    __device__ int after_step(WaveSlot &s) const
+    // Once the draw count has reached the replication's limit: completion,
+    // retention, abort, end of replay (the one-lane sampler's rules).
+    __device__ void after_step(GroupSlot &s) const
     {
         const uint32_t d = s.t;
         const bool capped = (s.tau == 0u) && (d >= D->capmax);
@@ -877,15 +883,14 @@ struct Coop {
             if (d == s.target) {
                 if (capped) truncation(s);
                 flush_slot(s);
-                return 2;
             }
-            return 0;
+            return;
         }
         if (ended) {
             if (capped) truncation(s);
             const uint64_t C = d;
             const bool retained = (s.r == 1u) || (s.S + C <= D->B);
-            if (!retained) { begin_rollback(s, d); return 1; }
+            if (!retained) { begin_rollback(s, d); return; }
             s.S += C;
             s.nret += 1u;
             stat_add(ST_RETAINED_UNITS, C);
@@ -901,28 +906,54 @@ struct Coop {
                 stat_max(ST_TAU_MAX, s.tau);
                 uint32_t bin = s.tau / D->hist_width;
                 if (bin >= a.hist_bins) bin = a.hist_bins - 1u;
-                if (lane == 0) atomicAdd(hist_lds + bin, 1u);
+                if (gl == 0) atomicAdd(hist_lds + bin, 1u);
             }
             if (s.r == 1u && C > D->B) stat_add(ST_ZERO_COMPLETION, 1);
-            if (!a.refill || s.S >= D->B || s.S + D->cmin > D->B) {
-                flush_slot(s);
-                return 2;
-            }
-            return 1;
+            if (!a.refill || s.S >= D->B || s.S + D->cmin > D->B) flush_slot(s);
+            else s.mode = MODE_NEED_REP;
+            return;
         }
-        if (s.r >= 2u && (uint64_t)d > D->B - s.S) {
-            begin_rollback(s, d);
-            return 1;
-        }
-        return 0;
+        if (s.r >= 2u && (uint64_t)d > D->B - s.S) begin_rollback(s, d);
     }
 
-    // One iteration: up to `span` draws from s.t, of which a prefix stands.
-    __device__ __forceinline__ void iterate(WaveSlot &s, uint32_t span)
+    __device__ __forceinline__ void start_rep(GroupSlot &s) const
+    {
+        if (s.sgn > 0) {
+            s.r += 1u;
+            stat_add(ST_REPS_STARTED, 1);
+        }
+        reset_state();
+        s.t = 0;
+        s.tau = 0;
+        s.mu = 0;
+        uint32_t lim = D->ell < D->capmax ? D->ell : D->capmax;
+        if (s.sgn < 0 && s.target < lim) lim = s.target;
+        if (s.r >= 2u) {
+            const uint64_t ab = D->B - s.S + 1u;
+            if (ab < (uint64_t)lim) lim = (uint32_t)ab;
+        }
+        s.lim = lim;
+        s.mode = MODE_RUN;
+    }
+
+    // One step of the group: up to gsz draws from s.t, of which a prefix stands.
+    __device__ __forceinline__ void iterate(GroupSlot &s) const
     {
         using R = Row<F>;
-        const uint32_t t = s.t + lane;
-        const bool act = lane < span;
+        // the next draw count at which something may have to be decided
+        uint32_t stop = D->capmax;
+        if (s.sgn < 0 && s.target < stop) stop = s.target;
+        if (s.r >= 2u) {
+            const uint64_t ab = D->B - s.S + 1u;
+            if (ab < (uint64_t)stop) stop = (uint32_t)ab;
+        }
+        if (s.t < D->ell && D->ell < stop) stop = D->ell;
+        uint32_t span = stop - s.t;
+        if (span > gsz) span = gsz;
+        if (s.t == 0u) span = 1u;
+
+        const uint32_t t = s.t + gl;
+        const bool act = gl < span;
         const bool updY = (s.tau == 0u) && (t > 0u);
         uint32_t blk[4];
         philox10(t >> 1, s.r, s.p, D->g, k0, k1, blk);
@@ -966,7 +997,7 @@ struct Coop {
             yn = (iy == ix) ? xn : decide(s, t, hw, thr[iy], have_lo, lo);
         }
         const bool flip = act && (xn != xi || yn != yi);
-        const uint64_t m = __ballot(flip);
+        const uint64_t m = (__ballot(flip) & gmask) >> leader;
         if (m == 0) {
             // at the pre-lag draw (span 1) a pair that did not move meets at t = 1
             if (s.tau == 0u && s.mu == 0) s.tau = s.t + 1u;
@@ -976,7 +1007,7 @@ struct Coop {
         const uint32_t f = (uint32_t)__builtin_ctzll(m);
         int dmu = 0;
         uint32_t ev = 0;
-        if (lane == f) {
+        if (gl == f) {
             const int dx = (int)xn - (int)xi;
             const int dy = (int)yn - (int)yi;
             st[bw_idx] = bw ^ ((uint32_t)(dx != 0) << sh) ^ ((uint32_t)(dy != 0) << (sh + 1u));
@@ -1002,12 +1033,12 @@ struct Coop {
                 ev = 1;
             }
         }
-        // f is wave-uniform: read lane f's results into scalar registers
-        dmu = __builtin_amdgcn_readlane(dmu, (int)f);
-        ev = __builtin_amdgcn_readlane(ev, (int)f);
-        const uint32_t If = __builtin_amdgcn_readlane(I, (int)f);
+        const int src = (int)(leader + f);
+        dmu = __shfl(dmu, src);
+        ev = __shfl(ev, src);
+        const uint32_t If = __shfl(I, src);
         if (ev && If != s.f0 && If != s.f1) {
-            if (lane == 0 && s.lc < a.list_cap)
+            if (gl == 0 && s.lc < a.list_cap)
                 __hip_atomic_store(list + s.lc, If, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             s.lc += 1u;
             s.f1 = s.f0;
@@ -1018,7 +1049,7 @@ struct Coop {
             if (s.mu == 0) s.tau = s.t + f + 1u;
         }
         s.t += f + 1u;
-        wave_fence();
+        lds_fence();
     }
 };
 
@@ -1027,6 +1058,9 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t lg = a.group_log2;                 // log2 of the lanes per group
+    const uint32_t gsz = 1u << lg, groups = 64u >> lg;
+    const uint32_t g = lane >> lg;
     uint32_t *hist_lds = smem + D->lds_hist;
     uint32_t *tab = smem + D->lds_tab;
     for (uint32_t b = tid; b < a.hist_bins; b += WG) hist_lds[b] = 0u;
@@ -1035,12 +1069,13 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
         copy_to_lds(tab + D->tab_off_alias / 4, D->alias, 1u << D->abits);
         copy_to_lds(tab + D->tab_off_rows / 4, D->rows, (uint32_t)D->n * D->row_bytes / 4u);
     }
-    __syncthreads();
-    uint32_t *st = smem + D->lds_state + wave * D->wave_words;
-    const size_t gw = (size_t)blockIdx.x * COOP_WAVES + wave;
-    uint64_t *ls = a.lane_stats + gw * ST_COUNT;
-    if (lane < (uint32_t)ST_COUNT) ls[lane] = 0;
+    const size_t gi = ((size_t)blockIdx.x * COOP_WAVES + wave) * groups + g;   // this group's rows
+    uint64_t *ls = a.lane_stats + gi * ST_COUNT;
+    const uint32_t gl = lane & (gsz - 1u);
+    for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) ls[i] = 0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
+    uint32_t *st = smem + D->lds_state + (wave * groups + g) * D->wave_words;
     Coop<TL, F> C{a,
                   D,
                   k0,
@@ -1050,67 +1085,56 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                   TL ? reinterpret_cast<const uint64_t *>(tab + D->tab_off_thr / 4) : D->thr,
                   TL ? tab + D->tab_off_alias / 4 : D->alias,
                   TL ? tab + D->tab_off_rows / 4 : D->rows,
-                  lane,
-                  a.acc + gw * (size_t)a.acc_stride,
-                  a.lists + gw * (size_t)a.list_cap,
+                  gl,
+                  gsz,
+                  g << lg,
+                  gsz == 64u ? ~0ull : (((1ull << gsz) - 1ull) << (g << lg)),
+                  a.acc + gi * (size_t)a.acc_stride,
+                  a.lists + gi * (size_t)a.list_cap,
                   hist_lds,
                   ls};
     const uint32_t P = D->P;
-    const uint32_t ell = D->ell, capmax = D->capmax;
+    GroupSlot s;
+    s.mode = MODE_NEED_SLOT;
+    s.p = s.r = s.t = s.nret = s.tau = s.target = s.lim = s.lc = 0;
+    s.f0 = s.f1 = NO_TAG;
+    s.mu = 0;
+    s.sgn = 1;
+    s.S = 0;
     for (;;) {
-        uint32_t p = 0;
-        if (lane == 0) p = atomicAdd(D->next_slot, 1u);
-        p = __builtin_amdgcn_readfirstlane(p);
-        if (p >= P) break;
-        WaveSlot s;
-        s.p = p;
-        s.r = s.t = s.nret = s.tau = s.target = s.lim = s.lc = 0;
-        s.f0 = s.f1 = NO_TAG;
-        s.mu = 0;
-        s.sgn = 1;
-        s.S = 0;
-        for (;;) {   // replications (and replays)
-            if (s.sgn > 0) {
-                s.r += 1u;
-                C.stat_add(ST_REPS_STARTED, 1);
+        if (s.mode == MODE_NEED_SLOT) {
+            uint32_t p = 0;
+            if (gl == 0) p = atomicAdd(D->next_slot, 1u);
+            p = __shfl(p, (int)(g << lg));
+            if (p >= P) {
+                s.mode = MODE_DONE;
+            } else {
+                s.p = p;
+                s.r = 0;
+                s.S = 0;
+                s.nret = 0;
+                s.lc = 0;
+                s.f0 = s.f1 = NO_TAG;
+                s.sgn = 1;
+                s.mode = MODE_NEED_REP;
             }
-            C.reset_state();
-            s.t = 0;
-            s.tau = 0;
-            s.mu = 0;
-            uint32_t lim = ell < capmax ? ell : capmax;
-            if (s.sgn < 0 && s.target < lim) lim = s.target;
-            if (s.r >= 2u) {
-                const uint64_t ab = D->B - s.S + 1u;
-                if (ab < (uint64_t)lim) lim = (uint32_t)ab;
-            }
-            int next = 0;
-            while (next == 0) {
-                // the next draw count at which something may have to be decided
-                uint32_t stop = capmax;
-                if (s.sgn < 0 && s.target < stop) stop = s.target;
-                if (s.r >= 2u) {
-                    const uint64_t ab = D->B - s.S + 1u;
-                    if (ab < (uint64_t)stop) stop = (uint32_t)ab;
-                }
-                if (s.t < ell && ell < stop) stop = ell;
-                uint32_t span = stop - s.t;
-                if (span > 64u) span = 64u;
-                if (s.t == 0u) span = 1u;
-                C.iterate(s, span);
-                if (s.t >= lim) next = C.after_step(s);
-            }
-            if (next == 2) break;
+        }
+        if (s.mode == MODE_NEED_REP) C.start_rep(s);
+        if (__all(s.mode == MODE_DONE)) break;
+        if (s.mode == MODE_RUN) {
+            C.iterate(s);
+            if (s.t >= s.lim) C.after_step(s);
         }
     }
-    // statistics: one atomic per counter and wave
-    if (lane < (uint32_t)ST_COUNT) {
-        const uint64_t v = __hip_atomic_load(ls + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // statistics: one atomic per counter and group
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) {
+        const uint64_t v = __hip_atomic_load(ls + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (v) {
-            if (lane == ST_TAU_MAX || lane == ST_NSTAR_MAX)
-                atomicMax(reinterpret_cast<unsigned long long *>(D->stats + lane), (unsigned long long)v);
+            if (i == ST_TAU_MAX || i == ST_NSTAR_MAX)
+                atomicMax(reinterpret_cast<unsigned long long *>(D->stats + i), (unsigned long long)v);
             else
-                atomicAdd(reinterpret_cast<unsigned long long *>(D->stats + lane), (unsigned long long)v);
+                atomicAdd(reinterpret_cast<unsigned long long *>(D->stats + i), (unsigned long long)v);
         }
     }
     __syncthreads();

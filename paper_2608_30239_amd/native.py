@@ -47,6 +47,8 @@ class RunOpts(C.Structure):
         ("narrow_lanes", C.c_uint32),
         ("bucket_rows", C.c_uint32),
         ("kernel", C.c_uint32),
+        ("group_lanes", C.c_uint32),
+        ("reserved", C.c_uint32),
         ("slot_nstar", C.c_void_p),
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),
@@ -62,7 +64,8 @@ STAT_FIELDS = ("progress_units", "retained_units", "single_site_updates", "reps_
 class RunStats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in STAT_FIELDS] + [
         ("placement", C.c_uint32), ("wg_per_cu", C.c_uint32), ("wg_slots", C.c_uint32),
-        ("kernel", C.c_uint32), ("kernel_ms", C.c_double)]
+        ("kernel", C.c_uint32), ("group_lanes", C.c_uint32), ("reserved", C.c_uint32),
+        ("kernel_ms", C.c_double)]
 
     def as_dict(self):
         d = {f: int(getattr(self, f)) for f in STAT_FIELDS}
@@ -70,13 +73,15 @@ class RunStats(C.Structure):
         d["wg_per_cu"] = int(self.wg_per_cu)
         d["wg_slots"] = int(self.wg_slots)
         d["kernel"] = int(self.kernel)
+        d["group_lanes"] = int(self.group_lanes)
         d["kernel_ms"] = float(self.kernel_ms)
         return d
 
 
 class TuneEntry(C.Structure):
     _fields_ = [("wg_per_cu", C.c_uint32), ("ticket_slots", C.c_uint32), ("narrow_lanes", C.c_uint32),
-                ("kernel", C.c_uint32), ("ms", C.c_double)]
+                ("kernel", C.c_uint32), ("group_lanes", C.c_uint32), ("reserved", C.c_uint32),
+                ("ms", C.c_double)]
 
 
 # Every symbol include/mcpd.h declares.
@@ -294,7 +299,8 @@ class Batch:
         cnt = C.c_uint32()
         _check(load().mcpd_batch_tune(self.h, seed, ent, cap, C.byref(cnt)), "mcpd_batch_tune")
         return [dict(wg_per_cu=int(e.wg_per_cu), ticket_slots=int(e.ticket_slots),
-                     narrow_lanes=int(e.narrow_lanes), kernel=int(e.kernel), ms=float(e.ms))
+                     narrow_lanes=int(e.narrow_lanes), kernel=int(e.kernel),
+                     group_lanes=int(e.group_lanes), ms=float(e.ms))
                 for e in ent[:cnt.value]]
 
     def config(self):

@@ -61,21 +61,23 @@ def run_batch(spec, seed, runs=1, **opt):
     return outs, cfg
 
 
-@pytest.mark.parametrize("kern", [1, 2], ids=["lane", "coop"])
+@pytest.mark.parametrize("kern", [dict(kernel=1), dict(kernel=2, group_lanes=16), dict(kernel=2, group_lanes=32)],
+                         ids=["lane", "coop16", "coop32"])
 def test_mixed_batch_matches_oracle_with_graph_replays(kern):
     spec = mixed_batch()
     base = 40
-    outs, cfg = run_batch(spec, seed=11, runs=3, instance_id=base, keep_slot_records=1, kernel=kern)
+    outs, cfg = run_batch(spec, seed=11, runs=3, instance_id=base, keep_slot_records=1, **kern)
     # every replay of the captured graph gives the same answer
     for r in outs[:-1]:
         for i in range(len(spec)):
             assert np.array_equal(r[i]["marginals"], outs[-1][i]["marginals"])
             assert np.array_equal(r[i]["hist"], outs[-1][i]["hist"])
-    if kern == 1:
+    if kern["kernel"] == 1:
         assert set(cfg["placement"].tolist()) >= {1, 3}
         assert (cfg["wg_slots"] < 256).any() and (cfg["wg_slots"] == 256).any()
     else:
-        assert ((cfg["placement"] & 5) == 5).all() and (cfg["wg_slots"] == 4).all()
+        assert ((cfg["placement"] & 5) == 5).all()
+        assert (cfg["wg_slots"] == 256 // kern["group_lanes"]).all()
     for i, (inst, budget, slots, k, m) in enumerate(spec):
         orc, nb = P.oracle_run(inst, budget, slots, k, m, seed=11, instance_id=base + i)
         P.check(outs[-1][i], orc, budget, slots, m)
@@ -87,7 +89,8 @@ def test_batch_invariant_to_launch_shape():
     shapes = [dict(kernel=1, wg_per_cu=2, ticket_slots=4), dict(kernel=1, wg_per_cu=3, ticket_slots=2),
               dict(plan=4, wg_per_cu=1), dict(kernel=1, use_graph=0, ticket_slots=8),
               dict(kernel=1, narrow_lanes=256), dict(kernel=1, narrow_lanes=32, wg_per_cu=2),
-              dict(kernel=2, wg_per_cu=3, ticket_slots=1), dict(kernel=2, plan=2, use_graph=0)]
+              dict(kernel=2, wg_per_cu=3, ticket_slots=1, group_lanes=64),
+              dict(kernel=2, plan=2, use_graph=0, group_lanes=8)]
     for sh in shapes:
         got, cfg = run_batch(spec, seed=5, **sh)
         if "wg_per_cu" in sh:
@@ -97,7 +100,7 @@ def test_batch_invariant_to_launch_shape():
         if sh.get("narrow_lanes") == 256:
             assert (cfg["wg_slots"] == 256).all() and (cfg["placement"] == 0).any()
         if sh.get("kernel") == 2:
-            assert (cfg["wg_slots"] == 4).all()
+            assert (cfg["wg_slots"] == 256 // sh["group_lanes"]).all()
         for a, b in zip(ref[0], got[0]):
             assert np.array_equal(a["bucket_sum"], b["bucket_sum"]), sh
             assert np.array_equal(a["bucket_sumsq"], b["bucket_sumsq"]), sh

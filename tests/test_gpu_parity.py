@@ -18,8 +18,9 @@ def _lib():
 
 
 # every generic case runs on both kernels: one slot per lane, and one slot
-# per wavefront with 64 speculative draws per step
-@pytest.fixture(params=[1, 2], ids=["lane", "coop"])
+# per group of 8, 16 or 64 lanes drawing speculatively
+@pytest.fixture(params=[dict(kernel=1), dict(kernel=2, group_lanes=8), dict(kernel=2, group_lanes=16),
+                        dict(kernel=2, group_lanes=64)], ids=["lane", "coop8", "coop16", "coop64"])
 def kern(request):
     return request.param
 
@@ -42,8 +43,9 @@ def compare(inst, budget, slots, k, m, seed=0, weights=None, tol=1e-12, **opt):
 
 def test_tiny_plain_one_pair_per_slot(kern):
     inst, rp = I.tiny_plain()
-    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed, kernel=kern)
-    assert gpu["stats"]["kernel"] == kern
+    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed, **kern)
+    assert gpu["stats"]["kernel"] == kern["kernel"]
+    assert gpu["stats"]["group_lanes"] == kern.get("group_lanes", 1)
     assert gpu["stats"]["reps_retained"] == rp.slots
 
 
@@ -52,19 +54,19 @@ def test_tiny_plain_one_pair_per_slot(kern):
 def test_tiny_refill_ragged(slots, mult, k, m, kern):
     inst, _ = I.tiny_plain()
     B = int(mult * max(m, 1))
-    gpu, orc = compare(inst, B * slots, slots, k, m, seed=3, hist_width=1, kernel=kern)
+    gpu, orc = compare(inst, B * slots, slots, k, m, seed=3, hist_width=1, **kern)
     if mult > 1:
         assert gpu["stats"]["reps_retained"] > slots
 
 
 def test_refill_off_and_instance_id(kern):
     inst, _ = I.tiny_plain()
-    compare(inst, 4096 * 200, 4096, 10, 50, seed=5, refill=0, instance_id=77, kernel=kern)
+    compare(inst, 4096 * 200, 4096, 10, 50, seed=5, refill=0, instance_id=77, **kern)
 
 
 def test_meeting_cap_truncation(kern):
     inst = I.make_instance("noisy12", 12, 6, 3, 2, 0.25, 0.25, prior=0.3, seed=3)
-    gpu, orc = compare(inst, 2000 * 30, 2000, 2, 6, seed=9, max_steps=8, hist_width=1, kernel=kern)
+    gpu, orc = compare(inst, 2000 * 30, 2000, 2, 6, seed=9, max_steps=8, hist_width=1, **kern)
     assert orc["stats"]["cap_hits"] > 0
 
 
@@ -72,20 +74,20 @@ def test_low_bit_refinement_path(kern):
     # u_hi_bits = 2 makes the high part of U tie with the threshold often,
     # so the low-bit block decides many draws
     inst, _ = I.tiny_plain()
-    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=2, kernel=kern)
-    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=13, kernel=kern)
+    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=2, **kern)
+    compare(inst, 512 * 150, 512, 10, 50, seed=2, u_hi_bits=13, **kern)
 
 
 def test_user_weights(kern):
     inst, _ = I.tiny_plain()
     w = np.linspace(1.0, 3.0, inst.n)
-    compare(inst, 2048 * 120, 2048, 10, 50, seed=4, weights=w, kernel=kern)
+    compare(inst, 2048 * 120, 2048, 10, 50, seed=4, weights=w, **kern)
 
 
 def test_degree_up_to_twelve_and_wide_pools(kern):
     inst = I.make_instance("deg12", 300, 200, (6, 12), 4, 0.08, 0.12, prior=4 / 300, seed=7)
     k, m = I.window_for_sweeps(1, inst.n)
-    compare(inst, 1024 * 4 * m, 1024, k, m, seed=1, kernel=kern)
+    compare(inst, 1024 * 4 * m, 1024, k, m, seed=1, **kern)
 
 
 def test_global_state_path():
@@ -104,8 +106,8 @@ def test_narrow_lds_layout():
     assert gpu["stats"]["placement"] == 1 and 8 <= gpu["stats"]["wg_slots"] < 256
     gpu2, _ = compare(inst, 512 * 700, 512, 10, 200, seed=6, narrow_lanes=256, kernel=1)
     assert gpu2["stats"]["placement"] in (0, 2) and gpu2["stats"]["wg_slots"] == 256
-    gpu3, _ = compare(inst, 512 * 700, 512, 10, 200, seed=6, kernel=2)
-    assert gpu3["stats"]["placement"] & 5 == 5 and gpu3["stats"]["wg_slots"] == 4
+    gpu3, _ = compare(inst, 512 * 700, 512, 10, 200, seed=6, kernel=2, group_lanes=32)
+    assert gpu3["stats"]["placement"] & 5 == 5 and gpu3["stats"]["wg_slots"] == 8
 
 
 def test_lds_state_global_tables():
@@ -136,8 +138,8 @@ def test_deterministic_repeat(kern):
     inst, rp = I.tiny_plain()
     dec = N.Decoder(inst)
     try:
-        a = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3, kernel=kern)
-        b = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3, kernel=kern)
+        a = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3, **kern)
+        b = dec.run(4096 * 150, 4096, 10, 50, seed=8, buckets=3, **kern)
     finally:
         dec.close()
     assert np.array_equal(a["marginals"], b["marginals"])
@@ -163,6 +165,6 @@ def test_invalid_arguments_raise():
 
 def test_paper_shaped_full_size(kern):
     inst, rp = I.paper_shaped()
-    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed, kernel=kern)
-    assert gpu["stats"]["placement"] & 3 == 3      # state and tables in LDS
+    gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed, **kern)
+    assert gpu["stats"]["placement"] & 1          # chain state in LDS
     assert gpu["stats"]["nstar_max"] >= 3
