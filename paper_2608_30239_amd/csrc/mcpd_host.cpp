@@ -282,9 +282,6 @@ struct Config {
     uint32_t group_log2 = 4;  // its lanes per slot: 2^group_log2 (3..6)
 };
 
-// Most workgroups of the cooperative kernel per CU (its registers allow 5
-// wavefronts per SIMD).
-constexpr uint32_t COOP_MAX_WG = 5;
 
 // Placement of one instance in a workgroup's LDS of `budget` bytes.
 struct Layout {
@@ -525,7 +522,7 @@ Config default_config(const Launch &L)
     c.narrow = narrow_of(L.opts);
     const uint32_t kernel = L.opts.kernel;
     const uint32_t lg = group_log2_of(L.opts);
-    const uint32_t cw = kernel == 1 ? 0u : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : COOP_MAX_WG, lg);
+    const uint32_t cw = kernel == 1 ? 0u : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : coop_waves_per_simd(L.fmt), lg);
     if (cw) {
         c.coop = true;
         c.group_log2 = lg;
@@ -625,15 +622,22 @@ int plan(Launch &L, const Config &c)
     L.slot_total = slots_total;
 
     // Tickets: longest slots first, each instance split into tickets of
-    // 256 * spl slots.
+    // (slots a workgroup runs at once) * spl slots.
     std::vector<size_t> order(count);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return L.desc[a].B > L.desc[b].B; });
-    L.tickets.clear();
-    for (size_t i : order) {
-        const uint64_t per_ticket = (uint64_t)L.desc[i].lanes * c.spl;
-        const uint64_t t = std::max<uint64_t>(1, (L.desc[i].P + per_ticket - 1) / per_ticket);
-        for (uint64_t j = 0; j < t; ++j) L.tickets.push_back((uint32_t)i);
+    // A ticket only lets one more workgroup join an instance (its slots are
+    // taken one by one), so when there are fewer tickets than resident
+    // workgroups the tickets shrink until every workgroup can join.
+    const size_t resident = (size_t)L.cus * c.wg_per_cu;
+    for (uint32_t spl = c.spl;; spl = std::max<uint32_t>(1, spl / 2)) {
+        L.tickets.clear();
+        for (size_t i : order) {
+            const uint64_t per_ticket = (uint64_t)L.desc[i].lanes * spl;
+            const uint64_t t = std::max<uint64_t>(1, (L.desc[i].P + per_ticket - 1) / per_ticket);
+            for (uint64_t j = 0; j < t; ++j) L.tickets.push_back((uint32_t)i);
+        }
+        if (spl == 1 || L.tickets.size() >= resident) break;
     }
     L.grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.cus * c.wg_per_cu, L.tickets.size()));
     const size_t lanes = (size_t)L.grid * WG_LANES;
@@ -1169,7 +1173,7 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
         const uint32_t lgs[] = {3, 4, 5, 6};
         for (uint32_t lg : lgs) {
             if (L.opts.group_lanes && lg != group_log2_of(L.opts)) continue;
-            const uint32_t top = coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : COOP_MAX_WG, lg);
+            const uint32_t top = coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : mcpd::coop_waves_per_simd(L.fmt), lg);
             if (!top) continue;
             Config c;
             c.coop = true;

@@ -80,8 +80,9 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
     for (int i = 0; i < 10; ++i) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // three-input xors (truth table 0x96) in one instruction each
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -1147,7 +1148,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
 // The cooperative variant of the persistent kernel (chain state always in
 // LDS, one slot per wave).
 template <int F>
-__global__ void __launch_bounds__(256) coop_kernel(LaunchArgs a)
+__global__ void __launch_bounds__(256, coop_waves_per_simd(F)) coop_kernel(LaunchArgs a)
 {
     extern __shared__ uint32_t smem[];
     __shared__ uint32_t sh_item, sh_skip;
