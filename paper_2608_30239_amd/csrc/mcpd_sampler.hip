@@ -717,7 +717,7 @@ __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
 constexpr uint32_t COOP_WAVES = WG / 64;   // wavefronts per workgroup
 
 struct GroupSlot {
-    uint32_t mode, p, r, t, nret, tau, target, lim, lc, f0, f1;
+    uint32_t mode, p, r, t, nret, tau, target, lim, stop, lc, f0, f1;
     int32_t mu, sgn;
     uint64_t S;
 };
@@ -785,10 +785,15 @@ struct Coop {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 
+    // All-negative state.  The count pair of pool m (one past the last pool)
+    // is a sentinel 0xFFFF: padding entries of a row read it and never find
+    // a free pool, so the speculative draws need no validity test.
     __device__ __forceinline__ void reset_state() const
     {
-        const uint32_t nw = D->words_bits + D->words_cnt;
+        const uint32_t m = D->m;
+        const uint32_t nw = D->words_bits + (m >> 1) + 1u;
         for (uint32_t w = gl; w < nw; w += gsz) st[w] = 0u;
+        if (gl == 0) cst[m >> 1] = (m & 1u) ? 0xFFFF0000u : 0xFFFFFFFFu;
         lds_fence();
     }
 
@@ -927,13 +932,16 @@ struct Coop {
         s.t = 0;
         s.tau = 0;
         s.mu = 0;
-        uint32_t lim = D->ell < D->capmax ? D->ell : D->capmax;
-        if (s.sgn < 0 && s.target < lim) lim = s.target;
+        // the first draw count past the window end at which the bookkeeping
+        // must look: the cap, the end of a replay, the abort point
+        uint32_t stop = D->capmax;
+        if (s.sgn < 0 && s.target < stop) stop = s.target;
         if (s.r >= 2u) {
             const uint64_t ab = D->B - s.S + 1u;
-            if (ab < (uint64_t)lim) lim = (uint32_t)ab;
+            if (ab < (uint64_t)stop) stop = (uint32_t)ab;
         }
-        s.lim = lim;
+        s.stop = stop;
+        s.lim = D->ell < stop ? D->ell : stop;
         s.mode = MODE_RUN;
     }
 
@@ -942,13 +950,7 @@ struct Coop {
     {
         using R = Row<F>;
         // the next draw count at which something may have to be decided
-        uint32_t stop = D->capmax;
-        if (s.sgn < 0 && s.target < stop) stop = s.target;
-        if (s.r >= 2u) {
-            const uint64_t ab = D->B - s.S + 1u;
-            if (ab < (uint64_t)stop) stop = (uint32_t)ab;
-        }
-        if (s.t < D->ell && D->ell < stop) stop = D->ell;
+        const uint32_t stop = (s.t < D->ell && D->ell < s.stop) ? D->ell : s.stop;
         uint32_t span = stop - s.t;
         if (span > gsz) span = gsz;
         if (s.t == 0u) span = 1u;
@@ -965,11 +967,14 @@ struct Coop {
         rc.load(rows, I);
         const uint32_t bw_idx = I >> 4;
         const uint32_t bw = st[bw_idx];
-        uint32_t cw[R::NE];
+        // (X, Y) count pair of each entry's pool: X in the low byte
+        const uint16_t *c16 = reinterpret_cast<const uint16_t *>(cst);
+        const uint32_t m = D->m;
+        uint32_t cp[R::NE];
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
-            const uint32_t v = rc.raw(e);
-            cw[e] = cst[(R::valid(v) ? R::pool(v) : 0u) >> 1];
+            const uint32_t j = R::pool(rc.raw(e));
+            cp[e] = c16[j < m ? j : m];
         }
         const uint32_t sh = (I & 15u) << 1;
         const uint32_t xi = (bw >> sh) & 1u;
@@ -977,12 +982,9 @@ struct Coop {
         uint32_t patX = 0, lenX = 0, patY = 0, lenY = 0;
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
-            const uint32_t v = rc.raw(e);
-            const bool ok = R::valid(v);
-            const uint32_t o = R::outcome(v);
-            const uint32_t c = cw[e] >> ((R::pool(v) & 1u) << 4);
-            const bool fx = ok && (c & 0xFFu) == xi;
-            const bool fy = ok && ((c >> 8) & 0xFFu) == yi;
+            const uint32_t o = R::outcome(rc.raw(e));
+            const bool fx = (cp[e] & 0xFFu) == xi;
+            const bool fy = (cp[e] >> 8) == yi;
             patX = fx ? ((patX << 1) | o) : patX;
             lenX += fx ? 1u : 0u;
             patY = fy ? ((patY << 1) | o) : patY;
@@ -998,28 +1000,31 @@ struct Coop {
             yn = (iy == ix) ? xn : decide(s, t, hw, thr[iy], have_lo, lo);
         }
         const bool flip = act && (xn != xi || yn != yi);
-        const uint64_t m = (__ballot(flip) & gmask) >> leader;
-        if (m == 0) {
+        const uint64_t fm = (__ballot(flip) & gmask) >> leader;
+        if (fm == 0) {
             // at the pre-lag draw (span 1) a pair that did not move meets at t = 1
             if (s.tau == 0u && s.mu == 0) s.tau = s.t + 1u;
             s.t += span;
             return;
         }
-        const uint32_t f = (uint32_t)__builtin_ctzll(m);
-        int dmu = 0;
-        uint32_t ev = 0;
+        const uint32_t f = (uint32_t)__builtin_ctzll(fm);
+        // the first changing lane applies its update and its estimator
+        // events, then tells the group (mu change + 1, event flag, site)
+        uint32_t msg = 0;
         if (gl == f) {
             const int dx = (int)xn - (int)xi;
             const int dy = (int)yn - (int)yi;
             st[bw_idx] = bw ^ ((uint32_t)(dx != 0) << sh) ^ ((uint32_t)(dy != 0) << (sh + 1u));
+            const uint32_t dxy = (uint32_t)dx + ((uint32_t)dy << 8);
 #pragma unroll
             for (int e = 0; e < R::NE; ++e) {
                 const uint32_t v = rc.raw(e);
                 if (!R::valid(v)) continue;
                 const uint32_t j = R::pool(v);
-                const uint32_t cs = (j & 1u) << 4;
-                cst[j >> 1] += ((uint32_t)dx << cs) + ((uint32_t)dy << (cs + 8u));
+                __hip_atomic_fetch_add(cst + (j >> 1), dxy << ((j & 1u) << 4), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
+            int dmu = 0;
             if (s.tau == 0u) dmu = (int)(xn != yn) - (int)(xi != yi);
             uint64_t val = 0;
             const uint32_t te = t + 1u;
@@ -1029,16 +1034,16 @@ struct Coop {
             }
             if (updY && t >= D->k + 1u && dx != dy)
                 val -= (uint64_t)(int64_t)(dx - dy) * gsum(t, D->k, D->ell, D->W);
+            uint32_t ev = 0;
             if (val != 0) {
                 add(I, s.sgn > 0 ? val : (uint64_t)0 - val);
                 ev = 1;
             }
+            msg = (uint32_t)(dmu + 1) | (ev << 2) | (I << 3);
         }
-        const int src = (int)(leader + f);
-        dmu = __shfl(dmu, src);
-        ev = __shfl(ev, src);
-        const uint32_t If = __shfl(I, src);
-        if (ev && If != s.f0 && If != s.f1) {
+        msg = __shfl(msg, (int)(leader + f));
+        const uint32_t If = msg >> 3;
+        if ((msg & 4u) && If != s.f0 && If != s.f1) {
             if (gl == 0 && s.lc < a.list_cap)
                 __hip_atomic_store(list + s.lc, If, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             s.lc += 1u;
@@ -1046,7 +1051,7 @@ struct Coop {
             s.f0 = If;
         }
         if (s.tau == 0u) {
-            s.mu += dmu;
+            s.mu += (int)(msg & 3u) - 1;
             if (s.mu == 0) s.tau = s.t + f + 1u;
         }
         s.t += f + 1u;
@@ -1097,31 +1102,35 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
     const uint32_t P = D->P;
     GroupSlot s;
     s.mode = MODE_NEED_SLOT;
-    s.p = s.r = s.t = s.nret = s.tau = s.target = s.lim = s.lc = 0;
+    s.p = s.r = s.t = s.nret = s.tau = s.target = s.lim = s.stop = s.lc = 0;
     s.f0 = s.f1 = NO_TAG;
     s.mu = 0;
     s.sgn = 1;
     s.S = 0;
     for (;;) {
-        if (s.mode == MODE_NEED_SLOT) {
-            uint32_t p = 0;
-            if (gl == 0) p = atomicAdd(D->next_slot, 1u);
-            p = __shfl(p, (int)(g << lg));
-            if (p >= P) {
-                s.mode = MODE_DONE;
-            } else {
-                s.p = p;
-                s.r = 0;
-                s.S = 0;
-                s.nret = 0;
-                s.lc = 0;
-                s.f0 = s.f1 = NO_TAG;
-                s.sgn = 1;
-                s.mode = MODE_NEED_REP;
+        // slot and replication changes (rare): one wave-wide test when every
+        // group is running
+        if (!__all(s.mode == MODE_RUN)) {
+            if (s.mode == MODE_NEED_SLOT) {
+                uint32_t p = 0;
+                if (gl == 0) p = atomicAdd(D->next_slot, 1u);
+                p = __shfl(p, (int)(g << lg));
+                if (p >= P) {
+                    s.mode = MODE_DONE;
+                } else {
+                    s.p = p;
+                    s.r = 0;
+                    s.S = 0;
+                    s.nret = 0;
+                    s.lc = 0;
+                    s.f0 = s.f1 = NO_TAG;
+                    s.sgn = 1;
+                    s.mode = MODE_NEED_REP;
+                }
             }
+            if (s.mode == MODE_NEED_REP) C.start_rep(s);
+            if (__all(s.mode == MODE_DONE)) break;
         }
-        if (s.mode == MODE_NEED_REP) C.start_rep(s);
-        if (__all(s.mode == MODE_DONE)) break;
         if (s.mode == MODE_RUN) {
             C.iterate(s);
             if (s.t >= s.lim) C.after_step(s);
