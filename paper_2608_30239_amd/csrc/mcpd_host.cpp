@@ -512,18 +512,43 @@ uint32_t coop_wg(const Launch &L, uint32_t most, uint32_t group_log2)
     return 0;
 }
 
+// Workgroups per CU for the cooperative kernel, at most `most`: the issue
+// rate of a CU is shared by its wavefronts, so a launch takes about
+// (rounds of slots) x (wavefronts per SIMD) slot-times, with rounds =
+// ceil(slots / slots running at once).  The count with the fewest is taken,
+// the larger on ties; a fractional last round leaves most groups idle.
+uint32_t coop_wg_for_rounds(const Launch &L, uint32_t most, uint32_t group_log2)
+{
+    uint64_t slots = 0;
+    for (const Item &it : L.items) slots += it.slots;
+    const uint64_t per_wg = (uint64_t)COOP_WAVES_PER_WG * (64u >> group_log2);
+    uint32_t best = most;
+    uint64_t best_cost = UINT64_MAX;
+    for (uint32_t w = most; w >= 1; --w) {
+        const uint64_t at_once = (uint64_t)L.cus * w * per_wg;
+        const uint64_t cost = ((slots + at_once - 1) / at_once) * w;
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = w;
+        }
+    }
+    return best;
+}
+
 // The default configuration.  The cooperative kernel when every instance's
-// chain states fit it (as many workgroups per CU as LDS and registers
-// allow).  Otherwise the lane kernel: one workgroup per CU when most of the
-// work keeps its chain state in LDS (that already takes the LDS), else as
-// many as the registers allow (more waves hide the latency of global state).
+// chain states fit it (workgroups per CU by coop_wg_for_rounds within what
+// LDS and registers allow).  Otherwise the lane kernel: one workgroup per CU
+// when most of the work keeps its chain state in LDS (that already takes the
+// LDS), else as many as the registers allow (more waves hide the latency of
+// global state).
 Config default_config(const Launch &L)
 {
     Config c;
     c.narrow = narrow_of(L.opts);
     const uint32_t kernel = L.opts.kernel;
     const uint32_t lg = group_log2_of(L.opts);
-    const uint32_t cw = kernel == 1 ? 0u : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : coop_waves_per_simd(L.fmt), lg);
+    uint32_t cw = kernel == 1 ? 0u : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : coop_waves_per_simd(L.fmt), lg);
+    if (cw && !L.opts.wg_per_cu) cw = coop_wg_for_rounds(L, cw, lg);
     if (cw) {
         c.coop = true;
         c.group_log2 = lg;
@@ -1182,6 +1207,12 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
             c.wg_per_cu = top;
             c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 4u;
             cands.push_back(c);
+            // and the count that leaves no fractional last round of slots
+            const uint32_t w = L.opts.wg_per_cu ? top : coop_wg_for_rounds(L, top, lg);
+            if (w != top) {
+                c.wg_per_cu = w;
+                cands.push_back(c);
+            }
         }
     }
     Config best = L.cfg;
