@@ -979,23 +979,30 @@ struct Coop {
         const uint32_t sh = (I & 15u) << 1;
         const uint32_t xi = (bw >> sh) & 1u;
         const uint32_t yi = (bw >> (sh + 1u)) & 1u;
-        uint32_t patX = 0, lenX = 0, patY = 0, lenY = 0;
+        uint32_t patX = 0, lenX = 0;
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
             const uint32_t o = R::outcome(rc.raw(e));
             const bool fx = (cp[e] & 0xFFu) == xi;
-            const bool fy = (cp[e] >> 8) == yi;
             patX = fx ? ((patX << 1) | o) : patX;
             lenX += fx ? 1u : 0u;
-            patY = fy ? ((patY << 1) | o) : patY;
-            lenY += fy ? 1u : 0u;
         }
         bool have_lo = false;
         uint64_t lo = 0;
         const uint32_t ix = (1u << lenX) - 1u + patX;
         const uint32_t xn = decide(s, t, hw, thr[ix], have_lo, lo);
         uint32_t yn = yi;
+        // most pairs meet within a few draws, after which only X moves: the
+        // Y pattern is built only while the pair has not met
         if (updY) {
+            uint32_t patY = 0, lenY = 0;
+#pragma unroll
+            for (int e = 0; e < R::NE; ++e) {
+                const uint32_t o = R::outcome(rc.raw(e));
+                const bool fy = (cp[e] >> 8) == yi;
+                patY = fy ? ((patY << 1) | o) : patY;
+                lenY += fy ? 1u : 0u;
+            }
             const uint32_t iy = (1u << lenY) - 1u + patY;
             yn = (iy == ix) ? xn : decide(s, t, hw, thr[iy], have_lo, lo);
         }
