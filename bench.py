@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
 # Peak 32-bit VALU issue: one lane-op per lane per clock (no packed ops).
 ALU_PEAK_OPS = CUS * SIMDS * LANES * CLOCK              # 3.93e13 lane-ops/s
+# LDS: 128 bytes per clock per CU.
+LDS_PEAK_BPS = CUS * 128 * CLOCK                        # 7.86e13 B/s
 
 
 def alg_ops_per_update(d: float) -> float:
@@ -183,9 +185,11 @@ def main():
         kernel_ms.append(r["stats"]["kernel_ms"])
     dt = time.perf_counter() - t0
     dec.close()
+    st = r["stats"]
     kernel_name = {1: "sampler_kernel (one slot per lane)",
-                   2: f"coop_kernel (one slot per {r['stats']['group_lanes']} lanes drawing speculatively)"}[
-        r["stats"]["kernel"]]
+                   2: f"coop_kernel (one slot per {st['group_lanes']} lanes drawing speculatively)"}[st["kernel"]]
+    kernel_name += (f", {st['wg_per_cu']} workgroups of 256 lanes per CU, chain state "
+                    f"{'and tables ' if st['placement'] & 2 else ''}in LDS, 5-entry rows")
 
     value = units / dt
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
@@ -198,10 +202,12 @@ def main():
         "unit": "Tops/s",
         "frac": achieved_ops / ALU_PEAK_OPS,
         "traffic": measured_traffic(),
-        "kernel": kernel_name + ", chain state and tables in LDS, 5-entry rows",
+        "kernel": kernel_name,
         "alg_ops_per_update": alg_ops_per_update(d_mean),
         "lds_bytes_per_update": lds_bytes_per_update(d_mean),
         "lds_achieved_TBps": lds_bytes_per_update(d_mean) * units_per_launch / avg_kernel_s / 1e12,
+        "lds_peak_TBps": LDS_PEAK_BPS / 1e12,
+        "lds_frac": lds_bytes_per_update(d_mean) * units_per_launch / avg_kernel_s / LDS_PEAK_BPS,
     }
     out = {
         "metric": "coupled Gibbs updates/s + marginal RMSE per GPU-second (learned vs score weights)",
