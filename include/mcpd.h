@@ -163,6 +163,24 @@ int mcpd_score_weights(int32_t n_clones, int32_t n_pools, const int32_t *row_ptr
                        const int32_t *pool_idx, const uint8_t *outcomes, double fp,
                        double fn, double prior, double *s_out, double *w_out);
 
+/* Pruning by the naive ranking (Section "Knill's Method": R_i, the product
+ * over the clone's pools of Pr{y_j|xi=1} / Pr{y_j|xi=0}; Section
+ * "Score-Weighted Update Gibbs Sampler": eta_i = log{q/(1-q)} + log R_i).
+ * Clones are ranked by log R_i, evaluated as n+_i a+ + n-_i a- in FP64
+ * (n+_i, n-_i: the clone's pools with y = 1 and y = 0; a+, a- as in
+ * mcpd_score_weights), so clones with equal counts tie exactly; ties go to
+ * the lower index.  The top n_active clones are retained; every other clone
+ * is fixed to 0, which makes the pruned posterior the posterior of the
+ * design restricted to the retained clones (all pools kept, prior
+ * unchanged): build that instance with mcpd_create.
+ *   design arguments as for mcpd_create (prior is not needed)
+ *   n_active  1..n_clones
+ *   active    host [n_active] out: the retained clones in ascending order
+ * Host-only, needs no device.  Errors: MCPD_EINVAL. */
+int mcpd_prune(int32_t n_clones, int32_t n_pools, const int32_t *row_ptr,
+               const int32_t *pool_idx, const uint8_t *outcomes, double fp, double fn,
+               int32_t n_active, int32_t *active);
+
 /* Create an instance: the pooling design A as a clone->pool CSR and the
  * observed pool outcomes y (Section "Knill's Method").
  *   n_clones, n_pools  > 0 (n_clones <= MCPD_MAX_CLONES, n_pools <= 32767)

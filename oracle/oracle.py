@@ -124,6 +124,28 @@ def score_weights(inst):
     return s, w
 
 
+def naive_rank(inst, n_active):
+    """The clones kept by pruning (Section "Knill's Method", naive ranking
+    R_i; Section "Score-Weighted Update Gibbs Sampler", eta_i): the n_active
+    clones of largest log R_i, ties to the lower index, returned in
+    ascending order.  log R_i = sum over the clone's pools of
+    log Pr{y_j|xi=1} - log Pr{y_j|xi=0}; grouped by outcome it is
+    n+_i a+ + n-_i a-, and that grouping is what is evaluated (in FP64), so
+    clones with the same outcome counts tie exactly."""
+    _, a_pos, a_neg = log_odds_terms(inst.fp, inst.fn, 0.5)
+    rp, pi, y = _design(inst)
+    n_pos = np.zeros(inst.n)
+    n_neg = np.zeros(inst.n)
+    for i in range(inst.n):
+        outs = y[pi[rp[i]:rp[i + 1]]]
+        n_pos[i] = float(np.count_nonzero(outs))
+        n_neg[i] = float(len(outs) - np.count_nonzero(outs))
+    key = n_pos * a_pos + n_neg * a_neg
+    # sort by key descending, then by index ascending
+    order = sorted(range(inst.n), key=lambda i: (-key[i], i))
+    return np.array(sorted(order[:n_active]), np.int32)
+
+
 def quantize(w):
     w = np.ascontiguousarray(w, np.float64)
     mass = np.zeros(len(w), np.uint64)

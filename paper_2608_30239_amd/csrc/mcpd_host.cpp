@@ -971,6 +971,31 @@ int mcpd_score_weights(int32_t n, int32_t m, const int32_t *row_ptr, const int32
     return MCPD_OK;
 }
 
+int mcpd_prune(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx, const uint8_t *y,
+               double fp, double fn, int32_t n_active, int32_t *active)
+{
+    using namespace mcpd::host;
+    // the prior plays no part in the ranking; 0.5 passes validation
+    int rc = validate_design(n, m, row_ptr, pool_idx, y, fp, fn, 0.5, nullptr);
+    if (rc) return rc;
+    if (!active) return fail(MCPD_EINVAL, "active is null");
+    if (n_active < 1 || n_active > n) return fail(MCPD_EINVAL, "n_active must be in 1..n_clones");
+    const double a_pos = std::log(1.0 - fn) - std::log(fp);
+    const double a_neg = std::log(fn) - std::log(1.0 - fp);
+    std::vector<double> key(n);
+    for (int32_t i = 0; i < n; ++i) {
+        double np = 0, nn = 0;
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) (y[pool_idx[e]] ? np : nn) += 1.0;
+        key[i] = np * a_pos + nn * a_neg;
+    }
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] > key[b]; });
+    std::sort(order.begin(), order.begin() + n_active);
+    std::memcpy(active, order.data(), sizeof(int32_t) * (size_t)n_active);
+    return MCPD_OK;
+}
+
 int mcpd_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx,
                 const uint8_t *y, double fp, double fn, double q, void *hip_stream, mcpd_instance **out)
 {

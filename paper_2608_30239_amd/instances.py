@@ -131,6 +131,44 @@ def from_dense(name, a: np.ndarray, y, fp, fn, prior) -> Instance:
                     np.zeros(0, np.int32))
 
 
+def restrict(inst: Instance, active, name: Optional[str] = None) -> Instance:
+    """The design restricted to the clones ``active`` (ascending), relabelled
+    0..len-1 in that order; every pool, the outcomes, the rates and the prior
+    are kept.  Clones outside ``active`` are fixed to 0, so this is the
+    instance of the pruned posterior."""
+    active = np.asarray(active, np.int64)
+    rows = [inst.pool_idx[inst.row_ptr[i]:inst.row_ptr[i + 1]] for i in active]
+    row_ptr, pool_idx = _csr_from_rows(rows)
+    where = {int(c): j for j, c in enumerate(active)}
+    pos = np.array([where[int(c)] for c in inst.positives if int(c) in where], np.int32)
+    return Instance(name or f"{inst.name}_top{len(active)}", len(active), inst.m, row_ptr, pool_idx,
+                    inst.y.copy(), inst.fp, inst.fn, inst.prior, pos)
+
+
+def regular_design(n: int, m: int, degree: int, pool_size: int, rng: np.random.Generator):
+    """A random design in which every clone is in ``degree`` distinct pools
+    and every pool holds ``pool_size`` clones (n * degree = m * pool_size):
+    pool slots dealt at random, then repeated pools inside a clone swapped
+    away with random slots of other clones."""
+    assert n * degree == m * pool_size
+    slots = np.repeat(np.arange(m, dtype=np.int32), pool_size)
+    rng.shuffle(slots)
+    rows = slots.reshape(n, degree)
+    for _ in range(1000 * n):
+        bad = [i for i in range(n) if len(set(rows[i].tolist())) < degree]
+        if not bad:
+            break
+        for i in bad:
+            e = int(rng.integers(degree))
+            j, f = int(rng.integers(n)), int(rng.integers(degree))
+            a, b = rows[i, e], rows[j, f]
+            if j != i and b not in rows[i] and a not in rows[j]:
+                rows[i, e], rows[j, f] = b, a
+    else:
+        raise RuntimeError("no regular design found")
+    return _csr_from_rows([np.sort(r) for r in rows])
+
+
 # --------------------------------------------------------------------------
 # Estimator-length recipe (supplementary, "Details of the Experimental Setup"
 # and Table S1): M_s = s * n_a updates, b_s = round(0.1 M_s), k = b_s + 1,
@@ -248,3 +286,40 @@ def heldout_large(seed: int, n: int = 20000, budget: int = 1 << 28) -> (Instance
     slots = 64 * -(-budget // (4 * n * 64))
     k, l = window_for_sweeps(1, n)
     return inst, RunParams(budget=budget, slots=slots, k=k, m=l, seed=0)
+
+
+# --------------------------------------------------------------------------
+# The designs of the paper's experiments (Section "Experimental Setup"), as
+# synthetic stand-ins: its 1298 x 97 instance and the Tapestry data are not
+# available, so designs of the same shape are drawn here.
+# --------------------------------------------------------------------------
+
+KNILL3_NOISE = ((0.05, 0.05), (0.05, 0.10), (0.10, 0.05), (0.10, 0.10))   # (fn, fp)
+
+
+def knill_degree3(fn: float = 0.10, fp: float = 0.10, seed: int = 0, design_seed: int = 0) -> Instance:
+    """1298 clones, 97 pools, every clone in 3 pools (random k-sets), 3
+    positives, q = 2.6 / 1298; the design held fixed over noise levels and
+    outcome seeds."""
+    return make_instance(f"knill3_fn{fn}_fp{fp}_s{seed}", 1298, 97, 3, 3, fp, fn, prior=2.6 / 1298,
+                         seed=seed, design_seed=design_seed)
+
+
+def tapestry_shaped(which: int = 320, seed: int = 0) -> (Instance, int):
+    """A design shaped like Tapestry 320 (320 samples, 48 pools of 20, 5
+    positives, fn = fp = 0.01, q = 5/320, all clones kept) or Tapestry 961
+    (961 samples, 93 pools of 31, 10 positives, fn = 1/23, fp = 0.01,
+    q = 10/961, 247 clones kept); every sample in 3 pools.  Returns the
+    instance and the number of clones the paper's analysis keeps."""
+    if which == 320:
+        n, m, size, npos, fn, fp, keep = 320, 48, 20, 5, 0.01, 0.01, 320
+    elif which == 961:
+        n, m, size, npos, fn, fp, keep = 961, 93, 31, 10, 1.0 / 23.0, 0.01, 247
+    else:
+        raise ValueError("which must be 320 or 961")
+    rng = np.random.default_rng([which, seed])
+    row_ptr, pool_idx = regular_design(n, m, 3, size, rng)
+    positives = np.sort(rng.choice(n, size=npos, replace=False)).astype(np.int32)
+    y = simulate_outcomes(row_ptr, pool_idx, m, positives, fp, fn, rng)
+    inst = Instance(f"tapestry{which}_s{seed}", n, m, row_ptr, pool_idx, y, fp, fn, npos / n, positives)
+    return inst, keep

@@ -85,7 +85,7 @@ class TuneEntry(C.Structure):
 
 
 # Every symbol include/mcpd.h declares.
-EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_create", "mcpd_set_weights",
+EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_prune", "mcpd_create", "mcpd_set_weights",
            "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_destroy", "mcpd_batch_create",
            "mcpd_batch_run", "mcpd_batch_tune", "mcpd_batch_config", "mcpd_batch_buckets",
            "mcpd_batch_slot_records", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_features",
@@ -122,6 +122,7 @@ def load(path: Optional[str] = None):
         L.mcpd_run_opts_init.restype = None
         L.mcpd_score_weights.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, C.c_double, C.c_double,
                                          C.c_double, vp, vp]
+        L.mcpd_prune.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, C.c_double, C.c_double, C.c_int32, vp]
         L.mcpd_create.argtypes = [C.c_int32, C.c_int32, vp, vp, vp, C.c_double, C.c_double,
                                   C.c_double, vp, C.POINTER(vp)]
         L.mcpd_set_weights.argtypes = [vp, vp]
@@ -184,6 +185,15 @@ def mcpd_score_weights(inst):
     _check(load().mcpd_score_weights(inst.n, inst.m, _p(rp), _p(pi), _p(y), inst.fp, inst.fn,
                                      inst.prior, _p(s), _p(w)), "mcpd_score_weights")
     return s, w
+
+
+def mcpd_prune(inst, n_active: int) -> np.ndarray:
+    """Indices (ascending) of the n_active clones the naive ranking keeps."""
+    rp, pi, y = _design(inst)
+    out = np.zeros(max(int(n_active), 1), np.int32)
+    _check(load().mcpd_prune(inst.n, inst.m, _p(rp), _p(pi), _p(y), inst.fp, inst.fn, int(n_active), _p(out)),
+           "mcpd_prune")
+    return out
 
 
 def mcpd_create(inst, stream: Optional[int] = None):
