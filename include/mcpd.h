@@ -91,7 +91,13 @@ typedef struct mcpd_run_opts {
                                MCPD_EINVAL if the states do not fit           */
     uint32_t group_lanes;   /* cooperative kernel: lanes per slot, 8, 16, 32 or
                                64 (0 = default 16)                            */
-    uint32_t reserved;
+    uint32_t init_mode;     /* initial distribution nu of every pair (Algorithm
+                               3: Z_0 ~ nu, X_0 = Y_0 = Z_0): 0 = all-negative
+                               state (default); 1 = the prior, clones
+                               independent with Pr{Z_0,i = 1} = floor(q 2^32)
+                               / 2^32, clone i drawn from word i mod 4 of the
+                               Philox block with counter (floor(i/4), r, p,
+                               g + 2^25); MCPD_EINVAL otherwise               */
     /* Optional host outputs of mcpd_run_unbiased (NULL = not wanted; must be
        NULL for batches). */
     uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */

@@ -499,6 +499,7 @@ typedef struct {
     uint64_t hist_width;
     uint64_t u_hi_bits;   /* b of draw_numbers, 1..32 */
     uint64_t instance_id; /* g, < 2^24 */
+    uint64_t init_mode;   /* nu: 0 = all-negative state, 1 = the prior */
 } mo_params;
 
 /* Sparse numerator accumulator: dense int64 values plus a touched list. */
@@ -632,6 +633,26 @@ static void trace_state(trace_t *tr, const scratch_t *s, int32_t n, uint64_t xt,
     if (with_y) memcpy(tr->Y + yt * (uint64_t)n, s->Y.x, (size_t)n);
 }
 
+/* Z_0 ~ nu for nu = the prior (reading; the paper leaves nu open): clones
+ * independent, Pr{Z_0,i = 1} = floor(q 2^32) / 2^32, clone i positive when
+ * its 32-bit uniform is below floor(q 2^32); the uniform of clone i is word
+ * i mod 4 of the Philox block with counter (floor(i/4), r, p, g + 2^25).
+ * X_0 = Y_0 = Z_0 (Algorithm 3). */
+static void draw_prior_state(const mo_model *M, const mo_params *P, uint32_t p, uint32_t r, scratch_t *s)
+{
+    const uint64_t Q = (uint64_t)floor(ldexp(M->q, 32));
+    const uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
+    for (int32_t i = 0; i < M->n; ++i) {
+        uint32_t ctr[4] = {(uint32_t)(i / 4), r, p, (uint32_t)P->instance_id + (1u << 25)};
+        uint32_t w[4];
+        mo_philox4x32_10(ctr, key, w);
+        if ((uint64_t)w[i % 4] < Q) {
+            chain_set(M, &s->X, i, 1);
+            chain_set(M, &s->Y, i, 1);
+        }
+    }
+}
+
 /* One coupled replication (Algorithm 3): X_0 = Y_0 = Z_0 ~ nu; the pre-lag
  * draw moves X only; every later draw (I_t, U_t) moves X_t -> X_{t+1} and
  * Y_{t-1} -> Y_t with the same numbers; tau_1 = inf{t >= 1 : X_t = Y_{t-1}};
@@ -650,6 +671,7 @@ static int run_replication(const mo_model *M, const mo_params *P, uint32_t p, ui
     chain_reset(M, &s->Y);
     while (s->nmis > 0) { s->mwhere[s->mis[s->nmis - 1]] = -1; s->nmis--; }
     acc_clear(&s->rep);
+    if (P->init_mode == 1) draw_prior_state(M, P, p, r, s);
 
     /* time index 0 */
     trace_state(tr, s, M->n, 0, 1, 0);
@@ -695,7 +717,7 @@ static int run_replication(const mo_model *M, const mo_params *P, uint32_t p, ui
 int mo_trace(const mo_model *M, const mo_params *P, uint32_t p, uint32_t r, uint64_t max_len,
              uint8_t *X, uint8_t *Y, int32_t *I, uint64_t *U, int64_t *numer, uint64_t out[3])
 {
-    if (P->k > P->ell || P->u_hi_bits < 1 || P->u_hi_bits > 32) return MO_EINVAL;
+    if (P->k > P->ell || P->u_hi_bits < 1 || P->u_hi_bits > 32 || P->init_mode > 1) return MO_EINVAL;
     scratch_t s;
     if (scratch_alloc(&s, M->n, M->m)) { scratch_free(&s); return MO_ENOMEM; }
     trace_t tr = {max_len, X, Y, I, U, 0};
@@ -808,7 +830,7 @@ int mo_run(const mo_model *M, const mo_params *P, double *marginals, double *std
     if (P->slots == 0 || P->slots > 0xFFFFFFFFull) return MO_EINVAL;
     if (P->k > P->ell || P->ell > (1ull << 31)) return MO_EINVAL;
     if (P->hist_bins == 0 || P->hist_width == 0) return MO_EINVAL;
-    if (P->u_hi_bits < 1 || P->u_hi_bits > 32) return MO_EINVAL;
+    if (P->u_hi_bits < 1 || P->u_hi_bits > 32 || P->init_mode > 1) return MO_EINVAL;
     if (P->instance_id >= (1ull << 24)) return MO_EINVAL;
     if (P->max_steps && P->max_steps < (P->ell > 1 ? P->ell : 1)) return MO_EINVAL;
     const int32_t n = M->n;
@@ -928,7 +950,7 @@ done:
 /* Numerator of one slot, dense (tests: sampled slots at full size). */
 int mo_slot(const mo_model *M, const mo_params *P, uint32_t p, int64_t *numer, uint64_t out[3])
 {
-    if (P->k > P->ell || P->u_hi_bits < 1 || P->u_hi_bits > 32 || P->slots == 0) return MO_EINVAL;
+    if (P->k > P->ell || P->u_hi_bits < 1 || P->u_hi_bits > 32 || P->slots == 0 || P->init_mode > 1) return MO_EINVAL;
     if (P->hist_bins == 0 || P->hist_width == 0) return MO_EINVAL;
     scratch_t s;
     if (scratch_alloc(&s, M->n, M->m)) { scratch_free(&s); return MO_ENOMEM; }

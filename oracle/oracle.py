@@ -44,7 +44,7 @@ def build(force: bool = False) -> str:
 class Params(C.Structure):
     _fields_ = [(name, C.c_uint64) for name in (
         "budget", "slots", "k", "ell", "seed", "max_steps", "refill", "hist_bins",
-        "hist_width", "u_hi_bits", "instance_id")]
+        "hist_width", "u_hi_bits", "instance_id", "init_mode")]
 
 
 def lib():
@@ -205,9 +205,9 @@ class Model:
 
     @staticmethod
     def params(budget, slots, k, m, seed=0, max_steps=0, refill=1, hist_bins=64,
-               hist_width=None, u_hi_bits=32, instance_id=0, n=None):
+               hist_width=None, u_hi_bits=32, instance_id=0, init_mode=0, n=None):
         return Params(budget, slots, k, m, seed, max_steps, refill, hist_bins,
-                      hist_width if hist_width else max(1, n or 1), u_hi_bits, instance_id)
+                      hist_width if hist_width else max(1, n or 1), u_hi_bits, instance_id, init_mode)
 
     def _params(self, **kw):
         kw.setdefault("n", self.n)

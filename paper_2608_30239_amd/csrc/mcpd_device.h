@@ -72,6 +72,7 @@ struct InstDesc {
     uint32_t cmin;          // max(ell, 1): cost of the cheapest replication
     uint32_t g;             // instance id in the random-number counter
     uint32_t hist_width;
+    uint32_t qthr;          // floor(q 2^32): Pr{Z_0,i = 1} of the prior initial state
     uint32_t nbuckets;      // rows of S1/S2
     // Placement in the launch's dynamic LDS (dword offsets).
     uint32_t place;         // Place bits
@@ -100,6 +101,7 @@ struct LaunchArgs {
     uint32_t acc_stride;        // >= every n
     uint32_t gwords;            // >= every global-state instance's words_bits + words_cnt
     uint32_t group_log2;        // cooperative kernel: log2 of the lanes that run one slot (3..6)
+    uint32_t init_mode;         // 0: all-negative initial state; 1: drawn from the prior
     const uint64_t *seed;       // device copy of the 64-bit key
     int64_t *acc;               // [lanes * acc_stride] spilled numerators (kept zero between slots)
     uint32_t *lists;            // [lanes * list_cap]
@@ -118,7 +120,7 @@ enum ErrFlag { ERR_BUCKETS = 1 };
 
 // Launch the sampler over a batch (defined in mcpd_sampler.hip); fmt is the
 // row format every instance's rows use.  Returns a hipError_t value as int.
-// coop: the cooperative kernel (one slot per wavefront, state in LDS).
+// coop: the cooperative kernel (one slot per group of lanes, state in LDS).
 int launch_sampler(const LaunchArgs &a, int fmt, int grid, size_t lds_bytes, void *stream, bool coop);
 template <int F>
 int launch_sampler_fmt(const LaunchArgs &a, int grid, size_t lds_bytes, void *stream, bool coop);

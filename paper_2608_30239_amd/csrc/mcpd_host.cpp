@@ -459,6 +459,7 @@ int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool bat
     if (o.kernel > 2) return fail(MCPD_EINVAL, "kernel must be 0 (auto), 1 (lane) or 2 (cooperative)");
     if (o.group_lanes && o.group_lanes != 8 && o.group_lanes != 16 && o.group_lanes != 32 && o.group_lanes != 64)
         return fail(MCPD_EINVAL, "group_lanes must be 0, 8, 16, 32 or 64");
+    if (o.init_mode > 1) return fail(MCPD_EINVAL, "init_mode must be 0 or 1");
     const uint64_t last_id = (uint64_t)o.instance_id + (batch_ids ? items.size() - 1 : 0);
     if (last_id >= (1u << 24)) return fail(MCPD_EINVAL, "instance ids must be < 2^24");
     for (const Item &it : items) {
@@ -623,6 +624,7 @@ int plan(Launch &L, const Config &c)
         d.W = it.m - it.k + 1;
         d.g = o.instance_id + (L.batch_ids ? (uint32_t)i : 0u);
         d.hist_width = o.hist_width ? o.hist_width : (uint32_t)I->n;
+        d.qthr = (uint32_t)std::floor(std::ldexp(I->q, 32));   // q < 1: below 2^32
         d.nbuckets = (uint32_t)std::max<uint64_t>(1, d.B / d.cmin);
         d.place = lay.place;
         d.lds_hist = lay.lds_hist;
@@ -735,6 +737,7 @@ LaunchArgs launch_args(const Launch &L)
     a.acc_stride = L.acc_stride;
     a.gwords = L.gwords;
     a.group_log2 = L.cfg.group_log2;
+    a.init_mode = L.opts.init_mode;
     a.seed = L.d_seed;
     a.acc = L.d_acc;
     a.lists = L.d_lists;

@@ -184,6 +184,38 @@ struct Sampler {
         for (uint32_t w = 0; w < nw; ++w) st[w * stride + lane] = 0u;
     }
 
+    // Initial state drawn from the prior (init_mode 1): clone i starts
+    // positive in both chains when word i mod 4 of the block (floor(i/4), r,
+    // p, g + 2^25) is below floor(q 2^32).  A positive start adds the W terms
+    // x_i(s) = 1, s = k..l, to the clone's numerator; later changes are
+    // events like any other.
+    __device__ __forceinline__ void init_prior(Lane &s) const
+    {
+        const uint32_t n = (uint32_t)D->n, nb = (n + 3u) >> 2;
+        const uint32_t q = D->qthr;
+        const uint64_t W = D->W;
+        for (uint32_t b = 0; b < nb; ++b) {
+            uint32_t w[4];
+            philox10(b, s.r, s.p, D->g | (1u << 25), k0, k1, w);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t i = 4u * b + (uint32_t)e;
+                if (i >= n || w[e] >= q) continue;
+                bits(i >> 4) |= 3u << ((i & 15u) << 1);
+                Row<F> rr;
+                rr.load(rows, i);
+#pragma unroll
+                for (int x = 0; x < Row<F>::NE; ++x) {
+                    const uint32_t v = rr.raw(x);
+                    if (!Row<F>::valid(v)) continue;
+                    const uint32_t j = Row<F>::pool(v);
+                    cnt(j >> 1) += 0x0101u << ((j & 1u) << 4);
+                }
+                event(s, i, s.sgn > 0 ? W : (uint64_t)0 - W);
+            }
+        }
+    }
+
     // First draw count at which after_step has anything to decide: the end of
     // the window, the cap, the end of a replay, or the abort point.
     __device__ __forceinline__ void set_limit(Lane &s) const
@@ -599,6 +631,7 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_
                     S.stat_add(ST_REPS_STARTED, 1);
                 }
                 S.reset_state();
+                if (a.init_mode) S.init_prior(s);
                 s.t = 0;
                 s.tau = 0;
                 s.mu = 0;
@@ -803,6 +836,55 @@ struct Coop {
                                __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
+    // Initial state drawn from the prior (init_mode 1), the group's lanes
+    // over blocks of 4 clones: clone i starts positive in both chains when
+    // word i mod 4 of the block (floor(i/4), r, p, g + 2^25) is below
+    // floor(q 2^32); its numerator gets the W terms x_i(s) = 1, s = k..l, and
+    // it joins the touched list (ballot-compacted).
+    __device__ __forceinline__ void init_prior(GroupSlot &s) const
+    {
+        using R = Row<F>;
+        const uint32_t n = (uint32_t)D->n, nb = (n + 3u) >> 2;
+        for (uint32_t b0 = 0; b0 < nb; b0 += gsz) {
+            const uint32_t b = b0 + gl;
+            uint32_t pm = 0;   // which of the block's 4 clones start positive
+            if (b < nb) {
+                uint32_t w[4];
+                philox10(b, s.r, s.p, D->g | (1u << 25), k0, k1, w);
+                const uint32_t q = D->qthr;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) pm |= (uint32_t)(w[e] < q && 4u * b + (uint32_t)e < n) << e;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t i = 4u * b + (uint32_t)e;
+                const bool pos = (pm >> e) & 1u;
+                const uint64_t m = (__ballot(pos) & gmask) >> leader;
+                if (pos) {
+                    __hip_atomic_fetch_or(st + (i >> 4), 3u << ((i & 15u) << 1), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                    R rr;
+                    rr.load(rows, i);
+#pragma unroll
+                    for (int x = 0; x < R::NE; ++x) {
+                        const uint32_t v = rr.raw(x);
+                        if (!R::valid(v)) continue;
+                        const uint32_t j = R::pool(v);
+                        __hip_atomic_fetch_add(cst + (j >> 1), 0x0101u << ((j & 1u) << 4), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    const uint64_t W = D->W;
+                    add(i, s.sgn > 0 ? W : (uint64_t)0 - W);
+                    const uint32_t at = s.lc + (uint32_t)__builtin_popcountll(m & ((1ull << gl) - 1ull));
+                    if (at < a.list_cap)
+                        __hip_atomic_store(list + at, i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                s.lc += (uint32_t)__builtin_popcountll(m);
+            }
+        }
+        lds_fence();
+    }
+
     __device__ __forceinline__ void emit(uint32_t nstar, uint32_t j, int64_t v) const
     {
         if (nstar > D->nbuckets) {
@@ -929,6 +1011,7 @@ struct Coop {
             stat_add(ST_REPS_STARTED, 1);
         }
         reset_state();
+        if (a.init_mode) init_prior(s);
         s.t = 0;
         s.tau = 0;
         s.mu = 0;

@@ -48,7 +48,7 @@ class RunOpts(C.Structure):
         ("bucket_rows", C.c_uint32),
         ("kernel", C.c_uint32),
         ("group_lanes", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("init_mode", C.c_uint32),
         ("slot_nstar", C.c_void_p),
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),

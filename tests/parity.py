@@ -40,7 +40,7 @@ def oracle_run(inst, budget, slots, k, m, seed=0, weights=None, nthreads=0, **op
     orc = M.run(budget, slots, k, m, seed=seed, nthreads=nthreads, slot_records=True, buckets=nb,
                 max_steps=opt.get("max_steps", 0), refill=opt.get("refill", 1),
                 hist_bins=hist_bins, hist_width=hist_width, u_hi_bits=opt.get("u_hi_bits", 32),
-                instance_id=opt.get("instance_id", 0))
+                instance_id=opt.get("instance_id", 0), init_mode=opt.get("init_mode", 0))
     orc["masses"] = M.masses()
     return orc, nb
 

@@ -40,7 +40,8 @@ def test_run_opts_defaults():
     o = N.run_opts()
     assert (o.max_steps, o.refill, o.strict_cap, o.hist_bins, o.hist_width, o.u_hi_bits,
             o.instance_id, o.plan, o.wg_per_cu, o.ticket_slots, o.use_graph,
-            o.keep_slot_records, o.narrow_lanes, o.kernel, o.group_lanes) == (0, 1, 0, 64, 0, 32, 0, 0, 0, 0, 1, 0, 0, 0, 0)
+            o.keep_slot_records, o.narrow_lanes, o.kernel, o.group_lanes, o.init_mode) == \
+        (0, 1, 0, 64, 0, 32, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0)
 
 
 def test_strerror_names_codes():

@@ -83,6 +83,16 @@ def test_mixed_batch_matches_oracle_with_graph_replays(kern):
         P.check(outs[-1][i], orc, budget, slots, m)
 
 
+def test_batch_prior_start_with_graph_replays():
+    spec = mixed_batch()
+    outs, _ = run_batch(spec, seed=19, runs=2, instance_id=7, init_mode=1, kernel=2, group_lanes=16)
+    for i in range(len(spec)):
+        assert np.array_equal(outs[0][i]["marginals"], outs[1][i]["marginals"])
+    for i, (inst, budget, slots, k, m) in enumerate(spec):
+        orc, nb = P.oracle_run(inst, budget, slots, k, m, seed=19, instance_id=7 + i, init_mode=1)
+        P.check(outs[-1][i], orc, budget, slots, m)
+
+
 def test_batch_invariant_to_launch_shape():
     spec = mixed_batch()
     ref, _ = run_batch(spec, seed=5)

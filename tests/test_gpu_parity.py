@@ -159,8 +159,36 @@ def test_invalid_arguments_raise():
             dec.run(0, 16, 1, 10, max_steps=5)  # cap below m
         with pytest.raises(N.McpdError):
             dec.set_weights(np.zeros(inst.n))
+        with pytest.raises(N.McpdError):
+            dec.run(0, 16, 1, 2, init_mode=2)  # no such initial distribution
     finally:
         dec.close()
+
+
+# the prior as initial distribution: clones start positive in both chains,
+# which adds window terms, count changes and touched-list entries at the
+# start of every replication (and of every replay)
+@pytest.mark.parametrize("slots,mult,k,m", [(1000, 2.5, 10, 50), (257, 3.3, 7, 7), (64, 9.0, 0, 20),
+                                            (1, 5.0, 3, 30)])
+def test_prior_start_ragged(slots, mult, k, m, kern):
+    inst, _ = I.tiny_plain()
+    inst.prior = 0.2
+    B = int(mult * max(m, 1))
+    gpu, orc = compare(inst, B * slots, slots, k, m, seed=3, hist_width=1, init_mode=1, **kern)
+    assert gpu["stats"]["reps_retained"] >= slots
+
+
+def test_prior_start_paper_shaped(kern):
+    inst, rp = I.paper_shaped()
+    compare(inst, 4096 * 4096, 4096, rp.k, rp.m, seed=8, init_mode=1, **kern)
+
+
+def test_prior_start_pruned_with_cap(kern):
+    full = I.knill_degree3(fn=0.1, fp=0.1)
+    inst = I.restrict(full, N.mcpd_prune(full, 333))
+    inst.prior = 0.01
+    k, l = I.window_for_sweeps(1, inst.n)
+    compare(inst, 20 * inst.n * 2048, 2048, k, l, seed=2, max_steps=20 * inst.n, init_mode=1, **kern)
 
 
 def test_paper_shaped_full_size(kern):
