@@ -8,9 +8,10 @@ resident in device memory before the timed region; every step runs the
 sampler kernel, the integer bucket reduction and the final FP64 division,
 with a new seed per step.
 
-Also reported on the same line: the two batched workloads (128-instance
-noise sweep, 256-instance uneven batch) as one persistent launch replayed
-from a captured graph, and the learned selection weights against the score
+Also reported on the same line: the batched workloads (128-instance noise
+sweep, 256-instance uneven batch uncapped and with the paper's meeting cap
+of 20 sweeps per instance) as one persistent launch replayed from a captured
+graph, and the learned selection weights against the score
 weights on the same paper-shaped workload at equal budget (RMSE against an
 independent long reference run, device seconds, efficiency 1/(MSE s)).
 
@@ -97,9 +98,12 @@ def batch_lines(steps: int):
     work = {"noise_sweep_128x1298": (insts, [(rp.budget, rp.slots, rp.k, rp.m)] * len(insts))}
     insts, params = I.uneven_batch()
     work["uneven_256"] = (insts, [(p.budget, p.slots, p.k, p.m) for p in params])
-    for name, (insts, params) in work.items():
+    # the same batch with the paper's meeting cap of 20 sweeps per instance
+    work["uneven_256_cap20sweeps"] = (insts, work["uneven_256"][1], dict(cap_sweeps=20))
+    for name, spec in work.items():
+        insts, params = spec[0], spec[1]
         decs = [N.Decoder(x) for x in insts]
-        bt = N.Batch(decs, params)
+        bt = N.Batch(decs, params, **(spec[2] if len(spec) > 2 else {}))
         try:
             tuned = bt.tune(12345)
             bt.run(12345, outputs=False)
@@ -113,7 +117,8 @@ def batch_lines(steps: int):
                              updates_per_s=units / (sum(ms) / 1e3), kernel=r[0]["stats"]["kernel"],
                              group_lanes=r[0]["stats"]["group_lanes"], wg_per_cu=cfg["wg_per_cu"],
                              ticket_slots=cfg["ticket_slots"], tuner_candidates=len(tuned),
-                             tau_max=max(x["stats"]["tau_max"] for x in r))
+                             tau_max=max(x["stats"]["tau_max"] for x in r),
+                             cap_hits=sum(x["stats"]["cap_hits"] for x in r))
         finally:
             bt.close()
             for d in decs:

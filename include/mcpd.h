@@ -98,6 +98,11 @@ typedef struct mcpd_run_opts {
                                / 2^32, clone i drawn from word i mod 4 of the
                                Philox block with counter (floor(i/4), r, p,
                                g + 2^25); MCPD_EINVAL otherwise               */
+    uint32_t cap_sweeps;    /* meeting cap in sweeps of each instance: a pair not
+                               met after max(cap_sweeps * n, m) draws stops as
+                               with max_steps (the paper's runs cap at 20
+                               sweeps); 0 = none; MCPD_EINVAL together with
+                               max_steps or when cap_sweeps * n >= 2^32     */
     /* Optional host outputs of mcpd_run_unbiased (NULL = not wanted; must be
        NULL for batches). */
     uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */

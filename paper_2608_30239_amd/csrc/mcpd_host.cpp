@@ -460,6 +460,7 @@ int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool bat
     if (o.group_lanes && o.group_lanes != 8 && o.group_lanes != 16 && o.group_lanes != 32 && o.group_lanes != 64)
         return fail(MCPD_EINVAL, "group_lanes must be 0, 8, 16, 32 or 64");
     if (o.init_mode > 1) return fail(MCPD_EINVAL, "init_mode must be 0 or 1");
+    if (o.max_steps && o.cap_sweeps) return fail(MCPD_EINVAL, "give max_steps or cap_sweeps, not both");
     const uint64_t last_id = (uint64_t)o.instance_id + (batch_ids ? items.size() - 1 : 0);
     if (last_id >= (1u << 24)) return fail(MCPD_EINVAL, "instance ids must be < 2^24");
     for (const Item &it : items) {
@@ -469,6 +470,8 @@ int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool bat
         const uint32_t cmin = std::max<uint32_t>(it.m, 1u);
         if (o.max_steps && (o.max_steps < cmin || o.max_steps > 0xFFFFFFFFull))
             return fail(MCPD_EINVAL, "max_steps must be 0 or in [max(m,1), 2^32-1]");
+        if ((uint64_t)o.cap_sweeps * (uint64_t)it.I->n > 0xFFFFFFFFull)
+            return fail(MCPD_EINVAL, "cap_sweeps * n must be below 2^32");
         const uint64_t B = it.budget / it.slots;
         const uint64_t nb = std::max<uint64_t>(1, B / cmin);
         if (nb * (uint64_t)it.I->n > (1ull << 27)) return fail(MCPD_EINVAL, "budget/slots/m give too many N* buckets");
@@ -617,7 +620,8 @@ int plan(Launch &L, const Config &c)
         d.lanes = lay.lanes;
         d.B = it.budget / it.slots;
         d.cmin = std::max<uint32_t>(it.m, 1u);
-        d.capmax = o.max_steps ? (uint32_t)std::max<uint64_t>(o.max_steps, it.m) : 0xFFFFFFFFu;
+        const uint64_t cap = o.max_steps ? o.max_steps : (uint64_t)o.cap_sweeps * (uint64_t)I->n;
+        d.capmax = cap ? (uint32_t)std::max<uint64_t>(cap, it.m) : 0xFFFFFFFFu;
         d.P = it.slots;
         d.k = it.k;
         d.ell = it.m;

@@ -49,6 +49,7 @@ class RunOpts(C.Structure):
         ("kernel", C.c_uint32),
         ("group_lanes", C.c_uint32),
         ("init_mode", C.c_uint32),
+        ("cap_sweeps", C.c_uint32),
         ("slot_nstar", C.c_void_p),
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),

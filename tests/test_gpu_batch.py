@@ -93,6 +93,30 @@ def test_batch_prior_start_with_graph_replays():
         P.check(outs[-1][i], orc, budget, slots, m)
 
 
+def test_batch_cap_in_sweeps_of_each_instance():
+    """cap_sweeps caps every instance at max(cap_sweeps * n_i, m_i) draws:
+    the oracle run of instance i with that max_steps."""
+    spec = mixed_batch()
+    outs, _ = run_batch(spec, seed=23, runs=1, instance_id=3, cap_sweeps=2)
+    capped = 0
+    for i, (inst, budget, slots, k, m) in enumerate(spec):
+        orc, nb = P.oracle_run(inst, budget, slots, k, m, seed=23, instance_id=3 + i,
+                               max_steps=max(2 * inst.n, m, 1))
+        P.check(outs[-1][i], orc, budget, slots, m)
+        capped += int(outs[-1][i]["stats"]["cap_hits"])
+    assert capped > 0
+    tiny, _ = I.tiny_plain()
+    dec = N.Decoder(tiny)
+    try:
+        a = dec.run(64 * 200, 64, 3, 40, 5, cap_sweeps=3)
+        b = dec.run(64 * 200, 64, 3, 40, 5, max_steps=48)
+        assert np.array_equal(a["marginals"], b["marginals"]) and a["stats"]["cap_hits"] > 0
+        with pytest.raises(N.McpdError):
+            dec.run(64 * 200, 64, 3, 40, 5, cap_sweeps=3, max_steps=48)
+    finally:
+        dec.close()
+
+
 def test_batch_invariant_to_launch_shape():
     spec = mixed_batch()
     ref, _ = run_batch(spec, seed=5)
