@@ -673,6 +673,9 @@ int plan(Launch &L, const Config &c)
     }
     L.grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.cus * c.wg_per_cu, L.tickets.size()));
     const size_t lanes = (size_t)L.grid * WG_LANES;
+    // numerator rows, touched lists and statistics rows: one per lane of the
+    // lane kernel, one per group of the cooperative kernel
+    const size_t rows = c.coop ? (size_t)L.grid * (WG_LANES >> c.group_log2) : lanes;
     // touched-clone lists long enough that large instances rarely fall back
     // to scanning a whole numerator row at the end of a slot
     L.list_cap = std::min<uint32_t>(4096, std::max<uint32_t>(64, L.acc_stride / 4));
@@ -680,16 +683,16 @@ int plan(Launch &L, const Config &c)
     // Workspace.  Numerator rows stay zero between runs (the kernel clears
     // what it used), so they are cleared only when (re)allocated.
     int rc;
-    const size_t acc_words = lanes * (size_t)L.acc_stride;
+    const size_t acc_words = rows * (size_t)L.acc_stride;
     if (acc_words > ((size_t)8 << 30)) return fail(MCPD_ENOMEM, "numerator workspace above 64 GiB; use fewer workgroups per CU");
     if (L.acc_cap < acc_words || !L.d_acc) {
         if ((rc = ensure(&L.d_acc, L.acc_cap, acc_words))) return rc;
         int e = launch_fill_zero(reinterpret_cast<uint64_t *>(L.d_acc), L.acc_cap, L.stream);
         if (e != hipSuccess) return hip_fail((hipError_t)e, "zero numerators");
     }
-    if ((rc = ensure(&L.d_lists, L.lists_cap, lanes * L.list_cap))) return rc;
+    if ((rc = ensure(&L.d_lists, L.lists_cap, rows * L.list_cap))) return rc;
     if (L.gwords && (rc = ensure(&L.d_gstate, L.gstate_cap, lanes * (size_t)L.gwords))) return rc;
-    if ((rc = ensure(&L.d_lane_stats, L.ls_cap, lanes * (size_t)ST_COUNT))) return rc;
+    if ((rc = ensure(&L.d_lane_stats, L.ls_cap, rows * (size_t)ST_COUNT))) return rc;
     if ((rc = ensure(&L.d_zero, L.zero_cap, L.zero_words))) return rc;
     if ((rc = ensure(&L.d_seed, L.seed_cap, (size_t)1))) return rc;
     if (L.slot_records) {
