@@ -773,6 +773,36 @@ struct Coop {
     uint32_t *list;         // its touched list
     uint32_t *hist_lds;
     uint64_t *ls;           // its statistics (global, written by the leader)
+    uint32_t gid;           // the group whose slot this is (index in the workgroup)
+
+    // Point at the state, numerator row, touched list and statistics of
+    // group `g` of this workgroup.
+    __device__ __forceinline__ void point(uint32_t *smem, uint32_t g)
+    {
+        gid = g;
+        st = smem + D->lds_state + g * D->wave_words;
+        cst = st + D->words_bits;
+        const size_t gi = (size_t)blockIdx.x * (COOP_WAVES * (64u >> a.group_log2)) + g;
+        acc = a.acc + gi * (size_t)a.acc_stride;
+        list = a.lists + gi * (size_t)a.list_cap;
+        ls = a.lane_stats + gi * ST_COUNT;
+    }
+
+    // The group's statistics into the instance's, once, when it runs out of
+    // slots (one atomic per counter).
+    __device__ __forceinline__ void flush_stats() const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) {
+            const uint64_t v = __hip_atomic_load(ls + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (v) {
+                if (i == ST_TAU_MAX || i == ST_NSTAR_MAX)
+                    atomicMax(reinterpret_cast<unsigned long long *>(D->stats + i), (unsigned long long)v);
+                else
+                    atomicAdd(reinterpret_cast<unsigned long long *>(D->stats + i), (unsigned long long)v);
+            }
+        }
+    }
 
     __device__ __forceinline__ void stat_add(int i, uint64_t v) const
     {
@@ -1165,19 +1195,13 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
         copy_to_lds(tab + D->tab_off_alias / 4, D->alias, 1u << D->abits);
         copy_to_lds(tab + D->tab_off_rows / 4, D->rows, (uint32_t)D->n * D->row_bytes / 4u);
     }
-    const size_t gi = ((size_t)blockIdx.x * COOP_WAVES + wave) * groups + g;   // this group's rows
-    uint64_t *ls = a.lane_stats + gi * ST_COUNT;
     const uint32_t gl = lane & (gsz - 1u);
-    for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) ls[i] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __syncthreads();
-    uint32_t *st = smem + D->lds_state + (wave * groups + g) * D->wave_words;
     Coop<TL, F> C{a,
                   D,
                   k0,
                   k1,
-                  st,
-                  st + D->words_bits,
+                  nullptr,
+                  nullptr,
                   TL ? reinterpret_cast<const uint64_t *>(tab + D->tab_off_thr / 4) : D->thr,
                   TL ? tab + D->tab_off_alias / 4 : D->alias,
                   TL ? tab + D->tab_off_rows / 4 : D->rows,
@@ -1185,10 +1209,15 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                   gsz,
                   g << lg,
                   gsz == 64u ? ~0ull : (((1ull << gsz) - 1ull) << (g << lg)),
-                  a.acc + gi * (size_t)a.acc_stride,
-                  a.lists + gi * (size_t)a.list_cap,
+                  nullptr,
+                  nullptr,
                   hist_lds,
-                  ls};
+                  nullptr,
+                  0u};
+    C.point(smem, wave * groups + g);
+    for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) C.ls[i] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __syncthreads();
     const uint32_t P = D->P;
     GroupSlot s;
     s.mode = MODE_NEED_SLOT;
@@ -1203,10 +1232,11 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
         if (!__all(s.mode == MODE_RUN)) {
             if (s.mode == MODE_NEED_SLOT) {
                 uint32_t p = 0;
-                if (gl == 0) p = atomicAdd(D->next_slot, 1u);
-                p = __shfl(p, (int)(g << lg));
+                if (C.gl == 0) p = atomicAdd(D->next_slot, 1u);
+                p = __shfl(p, (int)C.leader);
                 if (p >= P) {
                     s.mode = MODE_DONE;
+                    C.flush_stats();
                 } else {
                     s.p = p;
                     s.r = 0;
@@ -1219,22 +1249,53 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                 }
             }
             if (s.mode == MODE_NEED_REP) C.start_rep(s);
+            // A group with no slot left joins its buddy (the aligned group of
+            // the same size next to it): with a running buddy, the merged
+            // group carries on the buddy's slot with twice the lanes and
+            // looks twice as far ahead; two finished groups merge so that
+            // they can join a larger running group later.  Every group size
+            // commits the same draws, so results do not change.
+            for (;;) {
+                const bool done = s.mode == MODE_DONE;
+                const uint32_t bl = (C.leader ^ C.gsz) & 63u;
+                const uint32_t bsz = __shfl(C.gsz, (int)bl);
+                const bool bdone = __shfl((uint32_t)done, (int)bl) != 0u;
+                const bool merge = C.gsz < 64u && bsz == C.gsz && (done || bdone);
+                if (!__any(merge)) break;
+                // the running group's leader; for two finished groups the lower one
+                const uint32_t lower = C.leader < bl ? C.leader : bl;
+                const int src = (int)(!done ? C.leader : (!bdone ? bl : lower));
+                GroupSlot t;
+                t.mode = __shfl(s.mode, src);
+                t.p = __shfl(s.p, src);
+                t.r = __shfl(s.r, src);
+                t.t = __shfl(s.t, src);
+                t.nret = __shfl(s.nret, src);
+                t.tau = __shfl(s.tau, src);
+                t.target = __shfl(s.target, src);
+                t.lim = __shfl(s.lim, src);
+                t.stop = __shfl(s.stop, src);
+                t.lc = __shfl(s.lc, src);
+                t.f0 = __shfl(s.f0, src);
+                t.f1 = __shfl(s.f1, src);
+                t.mu = __shfl(s.mu, src);
+                t.sgn = __shfl(s.sgn, src);
+                t.S = ((uint64_t)__shfl((uint32_t)(s.S >> 32), src) << 32) | (uint64_t)__shfl((uint32_t)s.S, src);
+                const uint32_t tg = __shfl(C.gid, src);
+                if (merge) {
+                    s = t;
+                    C.leader = lower;
+                    C.gsz *= 2u;
+                    C.gl = lane - C.leader;
+                    C.gmask = C.gsz == 64u ? ~0ull : (((1ull << C.gsz) - 1ull) << C.leader);
+                    C.point(smem, tg);
+                }
+            }
             if (__all(s.mode == MODE_DONE)) break;
         }
         if (s.mode == MODE_RUN) {
             C.iterate(s);
             if (s.t >= s.lim) C.after_step(s);
-        }
-    }
-    // statistics: one atomic per counter and group
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) {
-        const uint64_t v = __hip_atomic_load(ls + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (v) {
-            if (i == ST_TAU_MAX || i == ST_NSTAR_MAX)
-                atomicMax(reinterpret_cast<unsigned long long *>(D->stats + i), (unsigned long long)v);
-            else
-                atomicAdd(reinterpret_cast<unsigned long long *>(D->stats + i), (unsigned long long)v);
         }
     }
     __syncthreads();
