@@ -237,6 +237,23 @@ int mcpd_run_unbiased(mcpd_instance *inst, uint64_t budget, uint32_t slots, uint
                       uint32_t m, uint64_t seed, const mcpd_run_opts *opts, double *marginals,
                       double *stderr_out, uint64_t *hist, mcpd_run_stats *stats);
 
+/* mcpd_run_unbiased with the outputs left in device memory (the same
+ * estimator, Algorithm 4 over Algorithm 3; the aggregate of Section
+ * "Coupled Estimator and Fixed-Budget GPU Execution"): the marginals and
+ * standard errors are formed on the device in FP64 from the same integer
+ * sums (mcpd_run_unbiased forms them on the host in extended precision, so
+ * the two agree to rounding), the histogram is copied device to device.
+ *   marginals_dev  device [n] (required), stderr_dev device [n] or NULL,
+ *   hist_dev       device [hist_bins] or NULL; all on the instance's device,
+ *                  owned by the caller, written in order on the instance's
+ *                  stream
+ *   stats          host, may be NULL
+ * Returns once the outputs are written.  Slot records and buckets (host
+ * outputs) are not accepted here.  Errors as mcpd_run_unbiased. */
+int mcpd_run_unbiased_dev(mcpd_instance *inst, uint64_t budget, uint32_t slots, uint32_t k,
+                          uint32_t m, uint64_t seed, const mcpd_run_opts *opts, double *marginals_dev,
+                          double *stderr_dev, uint64_t *hist_dev, mcpd_run_stats *stats);
+
 /* Release the instance and its device memory (NULL is a no-op).  Destroy
  * every batch that holds the instance first. */
 void mcpd_destroy(mcpd_instance *inst);

@@ -406,6 +406,11 @@ struct Launch {
     std::vector<size_t> slot_off;  // offset of each item's slot records
     size_t zero_words = 0, slot_total = 0;
     bool slot_records = false;
+    // device outputs of a single run (mcpd_run_unbiased_dev): when set, the
+    // copy back holds only the control word and item 0's counters and
+    // histogram
+    double *dev_marginals = nullptr, *dev_stderr = nullptr;
+    uint64_t *dev_hist = nullptr;
     // device workspace
     InstDesc *d_desc = nullptr; size_t desc_cap = 0;
     uint32_t *d_tickets = nullptr; size_t tickets_cap = 0;
@@ -765,7 +770,22 @@ int enqueue(Launch &L, bool timed)
     e = launch_sampler(launch_args(L), L.fmt, L.grid, L.lds, L.stream, L.coop);
     if (e != hipSuccess) return hip_fail((hipError_t)e, "sampler launch");
     if (timed) HIP_TRY(hipEventRecord(L.ev1, L.stream));
-    HIP_TRY(hipMemcpyAsync(L.h_out, L.d_zero, L.zero_words * 8, hipMemcpyDeviceToHost, L.stream));
+    if (L.dev_marginals) {
+        const InstDesc &d = L.desc[0];
+        const size_t n = (size_t)d.n, nb = L.nb[0];
+        const uint64_t *blk = L.d_zero + L.off[0];
+        const uint64_t *h = blk + 1 + ST_COUNT;
+        const int64_t *S1 = reinterpret_cast<const int64_t *>(h + L.opts.hist_bins);
+        const uint64_t *S2 = h + L.opts.hist_bins + nb * n;
+        e = launch_finish(S1, S2, (uint32_t)n, (uint32_t)nb, d.P, d.W, L.dev_marginals, L.dev_stderr, L.stream);
+        if (e != hipSuccess) return hip_fail((hipError_t)e, "finish launch");
+        if (L.dev_hist)
+            HIP_TRY(hipMemcpyAsync(L.dev_hist, h, L.opts.hist_bins * 8, hipMemcpyDeviceToDevice, L.stream));
+        HIP_TRY(hipMemcpyAsync(L.h_out, L.d_zero, (L.off[0] + 1 + ST_COUNT + L.opts.hist_bins) * 8,
+                               hipMemcpyDeviceToHost, L.stream));
+    } else {
+        HIP_TRY(hipMemcpyAsync(L.h_out, L.d_zero, L.zero_words * 8, hipMemcpyDeviceToHost, L.stream));
+    }
     return MCPD_OK;
 }
 
@@ -1097,13 +1117,15 @@ int mcpd_get_weights(const mcpd_instance *I, double *w_exact, uint64_t *mass)
     return MCPD_OK;
 }
 
-int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, uint32_t m,
-                      uint64_t seed, const mcpd_run_opts *opts_in, double *marginals, double *stderr_out,
-                      uint64_t *hist, mcpd_run_stats *stats)
+namespace mcpd {
+namespace host {
+// One fixed-budget run of one instance; device outputs when dev_marginals is
+// set (then marginals, stderr_out and hist are ignored).
+int run_single(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, uint32_t m, uint64_t seed,
+               const mcpd_run_opts *opts_in, double *marginals, double *stderr_out, uint64_t *hist,
+               mcpd_run_stats *stats, double *dev_marginals, double *dev_stderr, uint64_t *dev_hist)
 {
-    using namespace mcpd::host;
     if (!I) return fail(MCPD_EINVAL, "null instance");
-    if (!marginals || !stderr_out) return fail(MCPD_EINVAL, "null output");
     mcpd_run_opts opts;
     if (opts_in) opts = *opts_in; else mcpd_run_opts_init(&opts);
     std::vector<Item> items{Item{I, budget, slots, k, m}};
@@ -1125,12 +1147,43 @@ int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_
     Config c = default_config(L);
     if (opts.kernel == 2 && !c.coop) return fail(MCPD_EINVAL, "the chain states do not fit the cooperative kernel");
     if ((rc = plan(L, c))) return rc;
-    if ((rc = execute(L, seed, false))) return rc;
+    L.dev_marginals = dev_marginals;
+    L.dev_stderr = dev_stderr;
+    L.dev_hist = dev_hist;
+    rc = execute(L, seed, false);
+    L.dev_marginals = L.dev_stderr = nullptr;
+    L.dev_hist = nullptr;
+    if (rc) return rc;
+    if (dev_marginals) return finish_item(L, 0, nullptr, nullptr, nullptr, stats);
     if (L.slot_records && (rc = copy_slot_records(L, 0, opts.slot_nstar, opts.slot_units))) return rc;
     if ((opts.bucket_sum || opts.bucket_sumsq) &&
         (rc = copy_buckets(L, 0, opts.bucket_rows, opts.bucket_sum, opts.bucket_sumsq)))
         return rc;
     return finish_item(L, 0, marginals, stderr_out, hist, stats);
+}
+}  // namespace host
+}  // namespace mcpd
+
+int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, uint32_t m,
+                      uint64_t seed, const mcpd_run_opts *opts, double *marginals, double *stderr_out,
+                      uint64_t *hist, mcpd_run_stats *stats)
+{
+    using namespace mcpd::host;
+    if (!marginals || !stderr_out) return fail(MCPD_EINVAL, "null output");
+    return run_single(I, budget, slots, k, m, seed, opts, marginals, stderr_out, hist, stats, nullptr, nullptr,
+                      nullptr);
+}
+
+int mcpd_run_unbiased_dev(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, uint32_t m,
+                          uint64_t seed, const mcpd_run_opts *opts, double *marginals_dev, double *stderr_dev,
+                          uint64_t *hist_dev, mcpd_run_stats *stats)
+{
+    using namespace mcpd::host;
+    if (!marginals_dev) return fail(MCPD_EINVAL, "null marginals_dev");
+    if (opts && (opts->slot_nstar || opts->slot_units || opts->bucket_sum || opts->bucket_sumsq))
+        return fail(MCPD_EINVAL, "slot records and buckets are host outputs of mcpd_run_unbiased");
+    return run_single(I, budget, slots, k, m, seed, opts, nullptr, nullptr, nullptr, stats, marginals_dev,
+                      stderr_dev, hist_dev);
 }
 
 void mcpd_destroy(mcpd_instance *I)

@@ -87,7 +87,7 @@ class TuneEntry(C.Structure):
 
 # Every symbol include/mcpd.h declares.
 EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_prune", "mcpd_create", "mcpd_set_weights",
-           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_destroy", "mcpd_batch_create",
+           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_run_unbiased_dev", "mcpd_destroy", "mcpd_batch_create",
            "mcpd_batch_run", "mcpd_batch_tune", "mcpd_batch_config", "mcpd_batch_buckets",
            "mcpd_batch_slot_records", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_features",
            "mcpd_mlp_create", "mcpd_mlp_get_params", "mcpd_mlp_set_params", "mcpd_mlp_forward",
@@ -131,6 +131,7 @@ def load(path: Optional[str] = None):
         L.mcpd_run_unbiased.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                         C.c_uint64, C.POINTER(RunOpts), vp, vp, vp,
                                         C.POINTER(RunStats)]
+        L.mcpd_run_unbiased_dev.argtypes = L.mcpd_run_unbiased.argtypes
         L.mcpd_destroy.argtypes = [vp]
         L.mcpd_destroy.restype = None
         L.mcpd_batch_create.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(RunOpts), vp, C.POINTER(vp)]
@@ -250,6 +251,18 @@ def mcpd_run_unbiased(h, n, budget, slots, k, m, seed=0, slot_records=False, buc
                                     C.byref(st)), "mcpd_run_unbiased")
     out.update(marginals=marg, stderr=se, hist=hist, stats=st.as_dict())
     return out
+
+
+def mcpd_run_unbiased_dev(h, budget, slots, k, m, seed, marginals_ptr, stderr_ptr=0, hist_ptr=0, **opt):
+    """Device outputs: the pointers are device addresses (ints) of n doubles,
+    n doubles and hist_bins uint64 on the instance's device.  Returns the
+    statistics dict."""
+    o = run_opts(**opt)
+    st = RunStats()
+    _check(load().mcpd_run_unbiased_dev(h, budget, slots, k, m, seed, C.byref(o), C.c_void_p(marginals_ptr),
+                                        C.c_void_p(stderr_ptr or None), C.c_void_p(hist_ptr or None),
+                                        C.byref(st)), "mcpd_run_unbiased_dev")
+    return st.as_dict()
 
 
 def mcpd_destroy(h):
@@ -445,6 +458,10 @@ class Decoder:
 
     def run(self, budget, slots, k, m, seed=0, **kw):
         return mcpd_run_unbiased(self.h, self.n, budget, slots, k, m, seed, **kw)
+
+    def run_dev(self, budget, slots, k, m, seed, marginals_ptr, stderr_ptr=0, hist_ptr=0, **kw):
+        """Outputs written to device memory (addresses as ints)."""
+        return mcpd_run_unbiased_dev(self.h, budget, slots, k, m, seed, marginals_ptr, stderr_ptr, hist_ptr, **kw)
 
     def close(self):
         if getattr(self, "h", None):
