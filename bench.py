@@ -183,10 +183,12 @@ def main():
         dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + 1000 + i)
     units = 0
     kernel_ms = []
+    site_updates = 0
     t0 = time.perf_counter()
     for i in range(args.steps):
         r = dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + i)
         units += r["stats"]["progress_units"]
+        site_updates += r["stats"]["single_site_updates"]
         kernel_ms.append(r["stats"]["kernel_ms"])
     dt = time.perf_counter() - t0
     dec.close()
@@ -231,7 +233,9 @@ def main():
                                "fp=0.05, fn=0.10, q=3/1298, budget 2^28 over 65536 slots, k=131, l=1298",
                    "slots": rp.slots, "budget": rp.budget, "k": rp.k, "m": rp.m},
         "kernel_ms": avg_kernel_s * 1e3,
+        "kernel_ms_median": sorted(kernel_ms)[len(kernel_ms) // 2],
         "kernel_updates_per_s": units_per_launch / avg_kernel_s,
+        "single_site_updates_per_s": site_updates / dt,
         "roofline": roofline,
     }
     if not args.no_batches:
