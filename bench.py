@@ -88,6 +88,25 @@ def cpu_baseline(inst, rp, threads: int, min_seconds: float = 10.0, max_runs: in
                        f"{units} coupled updates in {dt:.2f} s")
 
 
+def cpu_baseline_one_thread(inst, rp, slots: int = 4096, min_seconds: float = 3.0):
+    """The oracle on one thread, on a bounded sample of the same workload:
+    its first `slots` slots at the same per-slot horizon B, new seeds until
+    at least min_seconds have passed."""
+    from oracle import oracle as O
+    M = O.Model(inst)
+    B = rp.budget // rp.slots
+    units, dt, runs = 0, 0.0, 0
+    while runs == 0 or dt < min_seconds:
+        t0 = time.perf_counter()
+        r = M.run(B * slots, slots, rp.k, rp.m, seed=rp.seed + runs, nthreads=1)
+        dt += time.perf_counter() - t0
+        units += r["stats"]["retained_units"] + r["stats"]["discarded_units"]
+        runs += 1
+    return dict(value=units / dt, unit="coupled Gibbs updates/s", cores=1, kind="oracle",
+                sample=f"{runs} runs of the first {slots} slots of the workload (B = {B}); "
+                       f"{units} coupled updates in {dt:.2f} s")
+
+
 def batch_lines(steps: int):
     """One persistent launch per batched workload, autotuned, then replayed
     from its captured graph."""
@@ -245,6 +264,7 @@ def main():
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(inst, rp, threads)
+        out["cpu_baseline_1thread"] = cpu_baseline_one_thread(inst, rp)
     print(json.dumps(out), flush=True)
 
 
