@@ -108,10 +108,17 @@ class Comparison:
             ms.append(r["stats"]["kernel_ms"])
         self.dec.set_weights(None)
         mse = float(np.mean(errs)) - self.ref_var
+        # the median run: the per-slot estimates are heavy-tailed (a pair
+        # that takes very long to meet makes one run's error large), so the
+        # mean over a few dozen runs is decided by its largest run; the
+        # median shows the typical run next to it
+        mse_med = float(np.median(errs)) - self.ref_var
         v = float(np.mean(var))
         sec = float(np.mean(ms)) / 1e3
         out = dict(mse=mse, rmse=float(np.sqrt(max(mse, 0.0))), seconds=sec,
                    efficiency=(1.0 / (mse * sec)) if mse > 0 else float("inf"),
+                   mse_median=mse_med,
+                   median_efficiency=(1.0 / (mse_med * sec)) if mse_med > 0 else float("inf"),
                    var=v, var_efficiency=1.0 / (v * sec), run_mse=errs, run_var=var, run_ms=ms)
         self.results[name] = out
         return out
@@ -233,6 +240,7 @@ def evaluate(net, nref=64, nrep=24, instances=None, log=print):
                    var_score=s["var"], var_learned=l["var"],
                    seconds_score=s["seconds"], seconds_learned=l["seconds"],
                    gain=cmp_.gain("learned"), var_gain=cmp_.gain("learned", key="var_efficiency"),
+                   median_gain=cmp_.gain("learned", key="median_efficiency"),
                    judge_choice=choice, judge_pilot_seconds=pilot_sec,
                    judged_gain=judged_eff / s["efficiency"], ref_var=cmp_.ref_var)
         rows.append(row)
@@ -241,7 +249,7 @@ def evaluate(net, nref=64, nrep=24, instances=None, log=print):
     def geomean(key):
         return float(np.exp(np.mean(np.log([max(r[key], 1e-12) for r in rows]))))
     return dict(rows=rows, gain_geomean=geomean("gain"), var_gain_geomean=geomean("var_gain"),
-                judged_gain_geomean=geomean("judged_gain"))
+                median_gain_geomean=geomean("median_gain"), judged_gain_geomean=geomean("judged_gain"))
 
 
 def load_trained(path=TRAINED):
