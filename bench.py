@@ -186,7 +186,7 @@ def main():
                     help="only run a device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the library runs one process on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib, max(1, args.steps))
