@@ -103,6 +103,15 @@ typedef struct mcpd_run_opts {
                                with max_steps (the paper's runs cap at 20
                                sweeps); 0 = none; MCPD_EINVAL together with
                                max_steps or when cap_sweeps * n >= 2^32     */
+    uint32_t first_slot;    /* global index of the run's first slot in the
+                               random-number counter (default 0): the run
+                               covers slots first_slot .. first_slot+slots-1
+                               of a larger run at the same horizon B, so a run
+                               split into such shares (say one per GPU) has
+                               integer sums, histogram and counters that add
+                               up exactly to the whole run's; slot records
+                               are indexed from the first slot;
+                               MCPD_EINVAL if first_slot + slots > 2^32     */
     /* Optional host outputs of mcpd_run_unbiased (NULL = not wanted; must be
        NULL for batches). */
     uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */

@@ -68,6 +68,7 @@ struct InstDesc {
     uint64_t B;             // per-slot horizon
     uint32_t capmax;        // draws after which an unmet pair stops
     uint32_t P;             // slots
+    uint32_t p0;            // global index of the first slot (random-number counter)
     uint32_t k, ell, W;     // window
     uint32_t cmin;          // max(ell, 1): cost of the cheapest replication
     uint32_t g;             // instance id in the random-number counter

@@ -477,6 +477,8 @@ int check_items(const std::vector<Item> &items, const mcpd_run_opts &o, bool bat
             return fail(MCPD_EINVAL, "max_steps must be 0 or in [max(m,1), 2^32-1]");
         if ((uint64_t)o.cap_sweeps * (uint64_t)it.I->n > 0xFFFFFFFFull)
             return fail(MCPD_EINVAL, "cap_sweeps * n must be below 2^32");
+        if ((uint64_t)o.first_slot + it.slots > (1ull << 32))
+            return fail(MCPD_EINVAL, "first_slot + slots must be at most 2^32");
         const uint64_t B = it.budget / it.slots;
         const uint64_t nb = std::max<uint64_t>(1, B / cmin);
         if (nb * (uint64_t)it.I->n > (1ull << 27)) return fail(MCPD_EINVAL, "budget/slots/m give too many N* buckets");
@@ -634,6 +636,7 @@ int plan(Launch &L, const Config &c)
         d.g = o.instance_id + (L.batch_ids ? (uint32_t)i : 0u);
         d.hist_width = o.hist_width ? o.hist_width : (uint32_t)I->n;
         d.qthr = (uint32_t)std::floor(std::ldexp(I->q, 32));   // q < 1: below 2^32
+        d.p0 = o.first_slot;
         d.nbuckets = (uint32_t)std::max<uint64_t>(1, d.B / d.cmin);
         d.place = lay.place;
         d.lds_hist = lay.lds_hist;

@@ -477,8 +477,8 @@ struct Sampler {
                 }
             }
         }
-        if (D->slot_nstar) D->slot_nstar[s.p] = nstar;
-        if (D->slot_units) D->slot_units[s.p] = s.S;
+        if (D->slot_nstar) D->slot_nstar[s.p - D->p0] = nstar;
+        if (D->slot_units) D->slot_units[s.p - D->p0] = s.S;
         stat_max(ST_NSTAR_MAX, nstar);
         s.mode = MODE_NEED_SLOT;
     }
@@ -615,7 +615,7 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_
                 if (p >= P) {
                     s.mode = MODE_DONE;
                 } else {
-                    s.p = p;
+                    s.p = p + D->p0;   // global slot index (the random-number counter)
                     s.r = 0;
                     s.S = 0;
                     s.nret = 0;
@@ -973,8 +973,8 @@ struct Coop {
             }
         }
         if (gl == 0) {
-            if (D->slot_nstar) D->slot_nstar[s.p] = nstar;
-            if (D->slot_units) D->slot_units[s.p] = s.S;
+            if (D->slot_nstar) D->slot_nstar[s.p - D->p0] = nstar;
+            if (D->slot_units) D->slot_units[s.p - D->p0] = s.S;
         }
         stat_max(ST_NSTAR_MAX, nstar);
         s.mode = MODE_NEED_SLOT;
@@ -1238,7 +1238,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                     s.mode = MODE_DONE;
                     C.flush_stats();
                 } else {
-                    s.p = p;
+                    s.p = p + D->p0;   // global slot index (the random-number counter)
                     s.r = 0;
                     s.S = 0;
                     s.nret = 0;

@@ -50,6 +50,7 @@ class RunOpts(C.Structure):
         ("group_lanes", C.c_uint32),
         ("init_mode", C.c_uint32),
         ("cap_sweeps", C.c_uint32),
+        ("first_slot", C.c_uint32),
         ("slot_nstar", C.c_void_p),
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     # mcpd_run_opts: u64, 16 x u32, 4 pointers; mcpd_run_stats: 14 x u64, 6 x u32, double
-    assert C.sizeof(N.RunOpts) == 8 + 17 * 4 + 4 + 4 * 8   # 4 bytes of padding before the pointers
+    assert C.sizeof(N.RunOpts) == 8 + 18 * 4 + 4 * 8
     assert C.sizeof(N.RunStats) == 14 * 8 + 6 * 4 + 8
     assert C.sizeof(N.TuneEntry) == 32
 
@@ -40,8 +40,8 @@ def test_run_opts_defaults():
     o = N.run_opts()
     assert (o.max_steps, o.refill, o.strict_cap, o.hist_bins, o.hist_width, o.u_hi_bits,
             o.instance_id, o.plan, o.wg_per_cu, o.ticket_slots, o.use_graph,
-            o.keep_slot_records, o.narrow_lanes, o.kernel, o.group_lanes, o.init_mode, o.cap_sweeps) == \
-        (0, 1, 0, 64, 0, 32, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 0)
+            o.keep_slot_records, o.narrow_lanes, o.kernel, o.group_lanes, o.init_mode, o.cap_sweeps, o.first_slot) == \
+        (0, 1, 0, 64, 0, 32, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 0, 0)
 
 
 def test_strerror_names_codes():
