@@ -63,7 +63,7 @@ struct InstDesc {
     uint32_t abits, row_bytes, thr_len;
     uint32_t words_bits, words_cnt;   // per-lane state words (bit pairs, count pairs)
     uint32_t lanes;         // slots a workgroup runs at once: active lanes (the LDS state
-                            // stride) of the lane kernel, or its wavefronts in the cooperative one
+                            // stride) of the lane kernel, or its groups in the cooperative one
     // Run parameters.
     uint64_t B;             // per-slot horizon
     uint32_t capmax;        // draws after which an unmet pair stops

@@ -276,7 +276,7 @@ struct Item {
 // Tuning knobs of a launch (results never depend on them).
 struct Config {
     uint32_t wg_per_cu = 1;   // workgroups of 256 lanes per compute unit
-    uint32_t spl = 1;         // slots per lane (or per wavefront) one ticket stands for
+    uint32_t spl = 1;         // slots per lane (or per group) one ticket stands for
     uint32_t narrow = 8;      // least lanes of a narrow LDS layout (0 = none)
     bool coop = false;        // the cooperative kernel (one slot per group of lanes)
     uint32_t group_log2 = 4;  // its lanes per slot: 2^group_log2 (3..6)
@@ -351,8 +351,8 @@ int layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, u
 }
 
 // Placement for the cooperative kernel: the histogram, the tables when they
-// fit, and one chain state per wavefront (words rounded to 16 bytes).
-// Returns false when the wavefronts' states do not fit.
+// fit, and one chain state per group of lanes (words rounded to 16 bytes).
+// Returns false when the groups' states do not fit.
 bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan,
                  uint32_t group_log2, Layout &L)
 {

@@ -1306,7 +1306,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
 }
 
 // The cooperative variant of the persistent kernel (chain state always in
-// LDS, one slot per wave).
+// LDS, one slot per group of lanes).
 template <int F>
 __global__ void __launch_bounds__(256, coop_waves_per_simd(F)) coop_kernel(LaunchArgs a)
 {
