@@ -91,10 +91,15 @@ struct InstDesc {
 };
 
 // Arguments of one launch over a batch of instances.
+// XCDs of the device: workgroup i of a launch runs on XCD i mod XCDS, and
+// each XCD has its own L2.
+constexpr uint32_t XCDS = 8;
+
 struct LaunchArgs {
     const InstDesc *inst;
     const uint32_t *tickets;    // [nticket]: instance index a workgroup joins
     uint32_t nticket;
+    uint32_t qoff[XCDS + 1];    // tickets of XCD x's queue: [qoff[x], qoff[x+1])
     uint32_t refill;
     uint32_t ubits;             // u_hi_bits
     uint32_t hist_bins;
@@ -108,7 +113,7 @@ struct LaunchArgs {
     uint32_t *lists;            // [lanes * list_cap]
     uint32_t *gstate;           // [lanes * gwords] chain state of global-state instances
     uint64_t *lane_stats;       // [lanes * ST_COUNT]
-    uint32_t *ctrl;             // [0]: next ticket, [1]: error flags (zeroed before the launch)
+    uint32_t *ctrl;             // [1]: error flags, [2 + x]: tickets taken from queue x (zeroed before the launch)
 };
 
 enum Stat {

@@ -38,6 +38,11 @@
 namespace mcpd {
 namespace host {
 
+// Control words at the head of the output block: [1] error flags, then one
+// ticket counter per XCD queue (u32 each).
+constexpr size_t CTRL_WORDS = (2 + XCDS + 1) / 2;
+
+
 thread_local std::string g_last_error;
 
 int fail(int code, const std::string &msg)
@@ -405,6 +410,7 @@ struct Launch {
     std::vector<uint32_t> nb;      // bucket rows per item
     std::vector<size_t> slot_off;  // offset of each item's slot records
     size_t zero_words = 0, slot_total = 0;
+    uint32_t qoff[XCDS + 1] = {};  // ticket queue of each XCD
     bool slot_records = false;
     // device outputs of a single run (mcpd_run_unbiased_dev): when set, the
     // copy back holds only the control word and item 0's counters and
@@ -597,7 +603,7 @@ int plan(Launch &L, const Config &c)
     L.lds = 0;
     L.acc_stride = 1;
     L.gwords = 0;
-    size_t words = 1;   // word 0: ticket counter and error flags
+    size_t words = CTRL_WORDS;   // control: error flags and the ticket queues' counters
     size_t slots_total = 0;
     for (size_t i = 0; i < count; ++i) {
         const Item &it = L.items[i];
@@ -661,10 +667,29 @@ int plan(Launch &L, const Config &c)
     L.zero_words = words;
     L.slot_total = slots_total;
 
-    // Tickets: longest slots first, each instance split into tickets of
-    // (slots a workgroup runs at once) * spl slots.
+    // Tickets: each instance split into tickets of (slots a workgroup runs at
+    // once) * spl slots, in one queue per XCD.  Instances go to the queues
+    // largest work first, each to the queue with the least work so far, so
+    // that an XCD's workgroups share few instances (their tables stay in that
+    // XCD's L2); within a queue, longest slots first.
     std::vector<size_t> order(count);
     std::iota(order.begin(), order.end(), 0);
+    std::vector<uint32_t> queue(count, 0);
+    {
+        std::vector<uint64_t> work(count);
+        for (size_t i = 0; i < count; ++i)
+            work[i] = std::max<uint64_t>(L.items[i].budget, (uint64_t)L.items[i].slots * L.desc[i].cmin);
+        std::vector<size_t> by_work(order);
+        std::stable_sort(by_work.begin(), by_work.end(), [&](size_t a, size_t b) { return work[a] > work[b]; });
+        uint64_t load[XCDS] = {};
+        for (size_t i : by_work) {
+            uint32_t x = 0;
+            for (uint32_t y = 1; y < XCDS; ++y)
+                if (load[y] < load[x]) x = y;
+            queue[i] = x;
+            load[x] += work[i];
+        }
+    }
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return L.desc[a].B > L.desc[b].B; });
     // A ticket only lets one more workgroup join an instance (its slots are
     // taken one by one), so when there are fewer tickets than resident
@@ -672,11 +697,16 @@ int plan(Launch &L, const Config &c)
     const size_t resident = (size_t)L.cus * c.wg_per_cu;
     for (uint32_t spl = c.spl;; spl = std::max<uint32_t>(1, spl / 2)) {
         L.tickets.clear();
-        for (size_t i : order) {
-            const uint64_t per_ticket = (uint64_t)L.desc[i].lanes * spl;
-            const uint64_t t = std::max<uint64_t>(1, (L.desc[i].P + per_ticket - 1) / per_ticket);
-            for (uint64_t j = 0; j < t; ++j) L.tickets.push_back((uint32_t)i);
+        for (uint32_t x = 0; x < XCDS; ++x) {
+            L.qoff[x] = (uint32_t)L.tickets.size();
+            for (size_t i : order) {
+                if (queue[i] != x) continue;
+                const uint64_t per_ticket = (uint64_t)L.desc[i].lanes * spl;
+                const uint64_t t = std::max<uint64_t>(1, (L.desc[i].P + per_ticket - 1) / per_ticket);
+                for (uint64_t j = 0; j < t; ++j) L.tickets.push_back((uint32_t)i);
+            }
         }
+        L.qoff[XCDS] = (uint32_t)L.tickets.size();
         if (spl == 1 || L.tickets.size() >= resident) break;
     }
     L.grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.cus * c.wg_per_cu, L.tickets.size()));
@@ -745,6 +775,7 @@ LaunchArgs launch_args(const Launch &L)
     a.inst = L.d_desc;
     a.tickets = L.d_tickets;
     a.nticket = (uint32_t)L.tickets.size();
+    for (uint32_t x = 0; x <= XCDS; ++x) a.qoff[x] = L.qoff[x];
     a.refill = L.opts.refill ? 1u : 0u;
     a.ubits = L.opts.u_hi_bits;
     a.hist_bins = L.opts.hist_bins;

@@ -697,6 +697,26 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_
 // is empty.  Every workgroup leaves when the ticket counter passes the end,
 // and every lane leaves an instance when its slot counter passes P, so the
 // grid always drains.
+// The next ticket of this workgroup: tickets come in one queue per XCD
+// (instances spread over the queues by work, so that the workgroups of one
+// XCD share few instances' tables in their L2); a workgroup takes from the
+// queue of its own XCD, then from the others in turn.  Returns nticket when
+// every queue is empty.  Queue counters only grow, so every workgroup
+// eventually sees them all empty.
+__device__ __forceinline__ uint32_t take_ticket(const LaunchArgs &a)
+{
+    const uint32_t home = blockIdx.x % XCDS;
+    for (uint32_t q = 0; q < XCDS; ++q) {
+        const uint32_t x = (home + q) % XCDS;
+        const uint32_t n = a.qoff[x + 1] - a.qoff[x];
+        if (n == 0) continue;
+        if (__hip_atomic_load(&a.ctrl[2 + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) continue;
+        const uint32_t it = atomicAdd(&a.ctrl[2 + x], 1u);
+        if (it < n) return a.qoff[x] + it;
+    }
+    return a.nticket;
+}
+
 template <int F>
 __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
 {
@@ -709,7 +729,7 @@ __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
         (const __attribute__((address_space(4))) uint32_t *)a.tickets;
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t it = atomicAdd(&a.ctrl[0], 1u);
+            const uint32_t it = take_ticket(a);
             uint32_t skip = 1;
             if (it < a.nticket) {
                 const InstDesc *d = a.inst + a.tickets[it];
@@ -1319,7 +1339,7 @@ __global__ void __launch_bounds__(256, coop_waves_per_simd(F)) coop_kernel(Launc
         (const __attribute__((address_space(4))) uint32_t *)a.tickets;
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t it = atomicAdd(&a.ctrl[0], 1u);
+            const uint32_t it = take_ticket(a);
             uint32_t skip = 1;
             if (it < a.nticket) {
                 const InstDesc *d = a.inst + a.tickets[it];
