@@ -28,6 +28,12 @@ __host__ __device__ constexpr int fmt_entries(int f)
          : f == FMT_U16_4 ? 4 : f == FMT_U16_8 ? 8 : 12;
 }
 __host__ __device__ constexpr bool fmt_wide(int f) { return f >= FMT_U16_4; }
+// Count words of the cooperative kernel's chain state: with one-byte entries
+// (fewer than 127 pools) one 32-bit word per pool, the X count in the low
+// half and the Y count in the high half, so that a count update is one LDS
+// add at the pool's word; with two-byte entries one 16-bit pair per pool (X
+// in the low byte), two pools per word, to keep large pool counts in LDS.
+__host__ __device__ constexpr bool coop_word_per_pool(int f) { return !fmt_wide(f); }
 __host__ __device__ constexpr int fmt_row_bytes(int f)
 {
     return f == FMT_U8_4 ? 4 : (f == FMT_U8_5 || f == FMT_U8_8 || f == FMT_U16_4) ? 8

@@ -362,8 +362,8 @@ bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t bud
                  uint32_t group_log2, Layout &L)
 {
     if (layout(I, fmt, hist_bins, budget, 4, 0, L)) return false;   // fills the sizes
-    // bit words, count pairs of pools 0..m-1 and the sentinel pair of pool m
-    const size_t words = (size_t)L.words_bits + (size_t)I->m / 2 + 1;
+    // bit words, counts of pools 0..m-1 and the sentinel of pool m
+    const size_t words = (size_t)L.words_bits + (coop_word_per_pool(fmt) ? (size_t)I->m : (size_t)I->m / 2) + 1;
     const size_t ww = (words + 3) & ~(size_t)3;
     const size_t groups = (size_t)COOP_WAVES_PER_WG * (64u >> group_log2);
     const size_t states = ww * groups * 4;

@@ -782,6 +782,7 @@ struct Coop {
     uint32_t k0, k1;
     uint32_t *st;           // this group's bit words (LDS)
     uint32_t *cst;          // its count words
+    static constexpr bool WPP = coop_word_per_pool(F);   // one count word per pool
     const uint64_t *thr;
     const uint32_t *alias;
     const uint32_t *rows;
@@ -868,16 +869,31 @@ struct Coop {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 
-    // All-negative state.  The count pair of pool m (one past the last pool)
-    // is a sentinel 0xFFFF: padding entries of a row read it and never find
+    // All-negative state.  The counts of pool m (one past the last pool) are
+    // a sentinel of all ones: padding entries of a row read it and never find
     // a free pool, so the speculative draws need no validity test.
     __device__ __forceinline__ void reset_state() const
     {
         const uint32_t m = D->m;
-        const uint32_t nw = D->words_bits + (m >> 1) + 1u;
+        const uint32_t nw = D->words_bits + (WPP ? m : (m >> 1)) + 1u;
         for (uint32_t w = gl; w < nw; w += gsz) st[w] = 0u;
-        if (gl == 0) cst[m >> 1] = (m & 1u) ? 0xFFFF0000u : 0xFFFFFFFFu;
+        if (gl == 0) {
+            if (WPP) cst[m] = 0xFFFFFFFFu;
+            else cst[m >> 1] = (m & 1u) ? 0xFFFF0000u : 0xFFFFFFFFu;
+        }
         lds_fence();
+    }
+
+    // Add (dx, dy) to the X and Y counts of pool j (two's complement, so a
+    // decrement of a positive count borrows nothing from the other count).
+    __device__ __forceinline__ void count_add(uint32_t j, int dx, int dy) const
+    {
+        if (WPP)
+            __hip_atomic_fetch_add(cst + j, (uint32_t)dx + ((uint32_t)dy << 16), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            __hip_atomic_fetch_add(cst + (j >> 1), ((uint32_t)dx + ((uint32_t)dy << 8)) << ((j & 1u) << 4),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
     __device__ __forceinline__ void add(uint32_t j, uint64_t v) const
@@ -920,8 +936,7 @@ struct Coop {
                         const uint32_t v = rr.raw(x);
                         if (!R::valid(v)) continue;
                         const uint32_t j = R::pool(v);
-                        __hip_atomic_fetch_add(cst + (j >> 1), 0x0101u << ((j & 1u) << 4), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        count_add(j, 1, 1);
                     }
                     const uint64_t W = D->W;
                     add(i, s.sgn > 0 ? W : (uint64_t)0 - W);
@@ -1100,14 +1115,17 @@ struct Coop {
         rc.load(rows, I);
         const uint32_t bw_idx = I >> 4;
         const uint32_t bw = st[bw_idx];
-        // (X, Y) count pair of each entry's pool: X in the low byte
+        // (X, Y) counts of each entry's pool: X in the low half (a 32-bit
+        // word per pool) or the low byte (a 16-bit pair per pool)
         const uint16_t *c16 = reinterpret_cast<const uint16_t *>(cst);
         const uint32_t m = D->m;
+        constexpr uint32_t CB = WPP ? 16u : 8u;          // bits of one count
+        constexpr uint32_t CM = (1u << CB) - 1u;
         uint32_t cp[R::NE];
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
             const uint32_t j = R::pool(rc.raw(e));
-            cp[e] = c16[j < m ? j : m];
+            cp[e] = WPP ? cst[j < m ? j : m] : (uint32_t)c16[j < m ? j : m];
         }
         const uint32_t sh = (I & 15u) << 1;
         const uint32_t xi = (bw >> sh) & 1u;
@@ -1116,7 +1134,7 @@ struct Coop {
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
             const uint32_t o = R::outcome(rc.raw(e));
-            const bool fx = (cp[e] & 0xFFu) == xi;
+            const bool fx = (cp[e] & CM) == xi;
             patX = fx ? ((patX << 1) | o) : patX;
             lenX += fx ? 1u : 0u;
         }
@@ -1132,7 +1150,7 @@ struct Coop {
 #pragma unroll
             for (int e = 0; e < R::NE; ++e) {
                 const uint32_t o = R::outcome(rc.raw(e));
-                const bool fy = (cp[e] >> 8) == yi;
+                const bool fy = (cp[e] >> CB) == yi;
                 patY = fy ? ((patY << 1) | o) : patY;
                 lenY += fy ? 1u : 0u;
             }
@@ -1155,14 +1173,11 @@ struct Coop {
             const int dx = (int)xn - (int)xi;
             const int dy = (int)yn - (int)yi;
             st[bw_idx] = bw ^ ((uint32_t)(dx != 0) << sh) ^ ((uint32_t)(dy != 0) << (sh + 1u));
-            const uint32_t dxy = (uint32_t)dx + ((uint32_t)dy << 8);
 #pragma unroll
             for (int e = 0; e < R::NE; ++e) {
                 const uint32_t v = rc.raw(e);
                 if (!R::valid(v)) continue;
-                const uint32_t j = R::pool(v);
-                __hip_atomic_fetch_add(cst + (j >> 1), dxy << ((j & 1u) << 4), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                count_add(R::pool(v), dx, dy);
             }
             int dmu = 0;
             if (s.tau == 0u) dmu = (int)(xn != yn) - (int)(xi != yi);
