@@ -60,6 +60,11 @@ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 constexpr size_t LDS_BYTES = 160 * 1024;
 
+// Dynamic LDS a workgroup may use when `wg` workgroups share a CU: the
+// kernels' static LDS (a few words) and the dynamic block together round up
+// to the 512-byte allocation granule, so one granule is set aside for them.
+size_t wg_lds_budget(uint32_t wg) { return (LDS_BYTES / wg - 512) & ~(size_t)511; }
+
 int validate_design(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx,
                     const uint8_t *y, double fp, double fn, double q, int32_t *dmax_out)
 {
@@ -243,17 +248,21 @@ int pick_format(bool wide, int need)
 }
 
 // Clone rows of an instance in format fmt (entry = pool | outcome << top
-// bit, ascending, padded with all-ones), uploaded on first use.
+// bit, ascending, padded with all-ones), uploaded on first use.  Rows of
+// FMT_U8_5 have three spare bytes; the last holds the outcome bits of the
+// entries (bit e = outcome of entry e).
 int rows_for(mcpd_instance *I, int fmt, const uint32_t **out)
 {
     if (!I->d_rows[fmt]) {
         const size_t rb = (size_t)fmt_row_bytes(fmt);
         std::vector<uint8_t> rowb((size_t)I->n * rb, 0xFFu);
         for (int32_t i = 0; i < I->n; ++i) {
+            const size_t at = (size_t)i * rb;
+            uint32_t om = 0;
             for (int32_t e = I->row_ptr[i]; e < I->row_ptr[i + 1]; ++e) {
                 const uint32_t j = (uint32_t)I->pool_idx[e], yj = I->y[j];
-                const size_t at = (size_t)i * rb;
                 const int32_t pos = e - I->row_ptr[i];
+                om |= yj << pos;
                 if (!fmt_wide(fmt)) {
                     rowb[at + pos] = (uint8_t)(j | (yj << 7));
                 } else {
@@ -261,6 +270,7 @@ int rows_for(mcpd_instance *I, int fmt, const uint32_t **out)
                     std::memcpy(&rowb[at + 2 * pos], &v, 2);
                 }
             }
+            if (fmt == FMT_U8_5) rowb[at + 7] = (uint8_t)om;
         }
         std::vector<uint32_t> rows(rowb.size() / 4);
         std::memcpy(rows.data(), rowb.data(), rowb.size());
@@ -367,15 +377,16 @@ bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t bud
     const size_t ww = (words + 3) & ~(size_t)3;
     const size_t groups = (size_t)COOP_WAVES_PER_WG * (64u >> group_log2);
     const size_t states = ww * groups * 4;
+    const size_t pat = coop_pattern_table(fmt) ? PATTERN_TABLE_BYTES : 0;   // at LDS offset 0
     const size_t hist = align16((size_t)hist_bins * 4u);
     if (plan == 3 || plan == 4) return false;   // plans that keep the state out of LDS
-    const bool tl = (plan == 0 || plan == 1) && hist + L.tab_bytes + states <= budget;
+    const bool tl = (plan == 0 || plan == 1) && pat + hist + L.tab_bytes + states <= budget;
     if (plan == 1 && !tl) return false;
-    if (hist + states > budget) return false;
+    if (pat + hist + states > budget) return false;
     L.lanes = (uint32_t)groups;
     L.place = PLACE_STATE_LDS | PLACE_COOP | (tl ? PLACE_TABLES_LDS : 0u);
-    L.lds_hist = 0;
-    L.lds_tab = (uint32_t)(hist / 4);
+    L.lds_hist = (uint32_t)(pat / 4);
+    L.lds_tab = (uint32_t)((pat + hist) / 4);
     L.lds_state = L.lds_tab + (tl ? L.tab_bytes / 4 : 0u);
     L.wave_words = (uint32_t)ww;
     L.used = (size_t)L.lds_state * 4 + states;
@@ -515,7 +526,7 @@ uint32_t narrow_of(const mcpd_run_opts &o)
 uint32_t coop_wg(const Launch &L, uint32_t most, uint32_t group_log2)
 {
     for (uint32_t wg = most; wg >= 1; --wg) {
-        const size_t budget = (LDS_BYTES / wg - 1024) & ~(size_t)1023;
+        const size_t budget = wg_lds_budget(wg);
         bool all = true;
         for (const Item &it : L.items) {
             Layout lay;
@@ -576,7 +587,7 @@ Config default_config(const Launch &L)
     double in_lds = 0, total = 0;
     for (const Item &it : L.items) {
         Layout lay;
-        if (layout(it.I, L.fmt, L.opts.hist_bins, LDS_BYTES - 1024, 0, narrow_of(L.opts), lay)) continue;
+        if (layout(it.I, L.fmt, L.opts.hist_bins, wg_lds_budget(1), 0, narrow_of(L.opts), lay)) continue;
         const double w = (double)it.budget + (double)it.slots;
         total += w;
         if (lay.place & PLACE_STATE_LDS) in_lds += w;
@@ -593,8 +604,7 @@ int plan(Launch &L, const Config &c)
     const mcpd_run_opts &o = L.opts;
     L.cfg = c;
     L.drop_graph();
-    // the kernel's own few bytes of static LDS come out of the same 160 KiB
-    const size_t budget = (LDS_BYTES / c.wg_per_cu - 1024) & ~(size_t)1023;
+    const size_t budget = wg_lds_budget(c.wg_per_cu);
     const size_t count = L.items.size();
     L.desc.assign(count, InstDesc{});
     L.off.assign(count, 0);

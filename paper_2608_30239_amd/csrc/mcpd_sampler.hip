@@ -783,6 +783,8 @@ struct Coop {
     uint32_t *st;           // this group's bit words (LDS)
     uint32_t *cst;          // its count words
     static constexpr bool WPP = coop_word_per_pool(F);   // one count word per pool
+    static constexpr bool PT = coop_pattern_table(F);    // threshold index from the pattern table
+    const uint8_t *pat8;    // the pattern table (LDS offset 0)
     const uint64_t *thr;
     const uint32_t *alias;
     const uint32_t *rows;
@@ -1130,31 +1132,39 @@ struct Coop {
         const uint32_t sh = (I & 15u) << 1;
         const uint32_t xi = (bw >> sh) & 1u;
         const uint32_t yi = (bw >> (sh + 1u)) & 1u;
-        uint32_t patX = 0, lenX = 0;
+        // threshold index of the free-pool outcome pattern (first free pool
+        // most significant): from the pattern table, or entry by entry
+        uint32_t om = 0;   // outcome bits of the clone's entries
+        if constexpr (F == FMT_U8_5) om = rc.w[R::WORDS - 1] >> 24;
+        else if constexpr (PT) om = ((rc.w[0] & 0x80808080u) * 0x00204081u) >> 28;   // bits 7, 15, 23, 31
+        auto index = [&](bool ych, uint32_t zi) {
+            if constexpr (PT) {
+                uint32_t fm = 0;
 #pragma unroll
-        for (int e = 0; e < R::NE; ++e) {
-            const uint32_t o = R::outcome(rc.raw(e));
-            const bool fx = (cp[e] & CM) == xi;
-            patX = fx ? ((patX << 1) | o) : patX;
-            lenX += fx ? 1u : 0u;
-        }
+                for (int e = 0; e < R::NE; ++e)
+                    fm |= (uint32_t)(((ych ? cp[e] >> CB : cp[e] & CM)) == zi) << e;
+                return (uint32_t)pat8[(om << 5) | fm];
+            } else {
+                uint32_t pat = 0, len = 0;
+#pragma unroll
+                for (int e = 0; e < R::NE; ++e) {
+                    const uint32_t o = R::outcome(rc.raw(e));
+                    const bool fz = (ych ? cp[e] >> CB : cp[e] & CM) == zi;
+                    pat = fz ? ((pat << 1) | o) : pat;
+                    len += fz ? 1u : 0u;
+                }
+                return (1u << len) - 1u + pat;
+            }
+        };
         bool have_lo = false;
         uint64_t lo = 0;
-        const uint32_t ix = (1u << lenX) - 1u + patX;
+        const uint32_t ix = index(false, xi);
         const uint32_t xn = decide(s, t, hw, thr[ix], have_lo, lo);
         uint32_t yn = yi;
         // most pairs meet within a few draws, after which only X moves: the
         // Y pattern is built only while the pair has not met
         if (updY) {
-            uint32_t patY = 0, lenY = 0;
-#pragma unroll
-            for (int e = 0; e < R::NE; ++e) {
-                const uint32_t o = R::outcome(rc.raw(e));
-                const bool fy = (cp[e] >> CB) == yi;
-                patY = fy ? ((patY << 1) | o) : patY;
-                lenY += fy ? 1u : 0u;
-            }
-            const uint32_t iy = (1u << lenY) - 1u + patY;
+            const uint32_t iy = index(true, yi);
             yn = (iy == ix) ? xn : decide(s, t, hw, thr[iy], have_lo, lo);
         }
         const bool flip = act && (xn != xi || yn != yi);
@@ -1237,6 +1247,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                   k1,
                   nullptr,
                   nullptr,
+                  reinterpret_cast<const uint8_t *>(smem),
                   TL ? reinterpret_cast<const uint64_t *>(tab + D->tab_off_thr / 4) : D->thr,
                   TL ? tab + D->tab_off_alias / 4 : D->alias,
                   TL ? tab + D->tab_off_rows / 4 : D->rows,
@@ -1352,6 +1363,24 @@ __global__ void __launch_bounds__(256, coop_waves_per_simd(F)) coop_kernel(Launc
     DescPtr descs = (DescPtr)a.inst;
     const __attribute__((address_space(4))) uint32_t *tickets =
         (const __attribute__((address_space(4))) uint32_t *)a.tickets;
+    if constexpr (coop_pattern_table(F)) {
+        // threshold index of every (outcome bits o, free mask f) of a clone's
+        // entries: the outcomes of the free entries in entry order, first
+        // most significant, as the pattern p of length |f| at (1 << |f|) - 1 + p
+        uint8_t *pt = reinterpret_cast<uint8_t *>(smem);
+        for (uint32_t x = threadIdx.x; x < PATTERN_TABLE_BYTES; x += WG) {
+            const uint32_t o = x >> 5, f = x & 31u;
+            uint32_t p = 0, len = 0;
+            for (uint32_t e = 0; e < 5u; ++e) {
+                if ((f >> e) & 1u) {
+                    p = (p << 1) | ((o >> e) & 1u);
+                    ++len;
+                }
+            }
+            pt[x] = (uint8_t)((1u << len) - 1u + p);
+        }
+        // visible to every wavefront after the ticket loop's first barrier
+    }
     for (;;) {
         if (threadIdx.x == 0) {
             const uint32_t it = take_ticket(a);
