@@ -35,9 +35,9 @@ __host__ __device__ constexpr bool fmt_wide(int f) { return f >= FMT_U16_4; }
 // in the low byte), two pools per word, to keep large pool counts in LDS.
 __host__ __device__ constexpr bool coop_word_per_pool(int f) { return !fmt_wide(f); }
 // Formats whose cooperative kernel finds the threshold index of a draw in a
-// 1 KB table at the start of LDS, indexed by the clone's outcome bits (5)
-// and the free mask of its pools (5), instead of building the pattern entry
-// by entry.  Rows of FMT_U8_5 carry the outcome bits in their last byte.
+// 1 KB table at the start of LDS, indexed by the free mask of the clone's
+// pools (5 bits, high) and its outcome bits (5), instead of building the
+// pattern entry by entry.  Rows of FMT_U8_5 carry the outcome bits in their last byte.
 __host__ __device__ constexpr bool coop_pattern_table(int f) { return f == FMT_U8_4 || f == FMT_U8_5; }
 constexpr uint32_t PATTERN_TABLE_BYTES = 1024;
 __host__ __device__ constexpr int fmt_row_bytes(int f)

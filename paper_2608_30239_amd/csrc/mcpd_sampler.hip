@@ -1143,7 +1143,7 @@ struct Coop {
 #pragma unroll
                 for (int e = 0; e < R::NE; ++e)
                     fm |= (uint32_t)(((ych ? cp[e] >> CB : cp[e] & CM)) == zi) << e;
-                return (uint32_t)pat8[(om << 5) | fm];
+                return (uint32_t)pat8[(fm << 5) | om];
             } else {
                 uint32_t pat = 0, len = 0;
 #pragma unroll
@@ -1364,12 +1364,14 @@ __global__ void __launch_bounds__(256, coop_waves_per_simd(F)) coop_kernel(Launc
     const __attribute__((address_space(4))) uint32_t *tickets =
         (const __attribute__((address_space(4))) uint32_t *)a.tickets;
     if constexpr (coop_pattern_table(F)) {
-        // threshold index of every (outcome bits o, free mask f) of a clone's
+        // threshold index of every (free mask f, outcome bits o) of a clone's
         // entries: the outcomes of the free entries in entry order, first
-        // most significant, as the pattern p of length |f| at (1 << |f|) - 1 + p
+        // most significant, as the pattern p of length |f| at (1 << |f|) - 1 + p.
+        // Free mask high: draws that find every pool free read 8 consecutive
+        // dwords whatever their outcome bits, with no bank conflicts.
         uint8_t *pt = reinterpret_cast<uint8_t *>(smem);
         for (uint32_t x = threadIdx.x; x < PATTERN_TABLE_BYTES; x += WG) {
-            const uint32_t o = x >> 5, f = x & 31u;
+            const uint32_t f = x >> 5, o = x & 31u;
             uint32_t p = 0, len = 0;
             for (uint32_t e = 0; e < 5u; ++e) {
                 if ((f >> e) & 1u) {

@@ -64,6 +64,19 @@ def test_refill_off_and_instance_id(kern):
     compare(inst, 4096 * 200, 4096, 10, 50, seed=5, refill=0, instance_id=77, **kern)
 
 
+@pytest.mark.parametrize("degree", [(1, 4), (1, 5), (4, 5)], ids=["u8x4-mixed", "u8x5-mixed", "u8x5-4or5"])
+def test_one_byte_rows_with_padding(degree, kern):
+    """Rows of one-byte entries (m <= 127) whose clones have fewer pools than
+    a row holds: the padding entries must never count as free pools, on the
+    lane kernel and on the cooperative kernel, which takes the threshold
+    index of 4- and 5-entry rows from its pattern table."""
+    inst = I.make_instance("pad", 400, 60, degree, 4, 0.08, 0.12, prior=4 / 400, seed=11)
+    d = inst.degrees()
+    assert d.min() < d.max() == degree[1] and inst.m <= 127
+    compare(inst, 256 * 3 * 400, 256, 41, 400, seed=12, **kern)
+    compare(inst, 256 * 3 * 400, 256, 41, 400, seed=13, init_mode=1, **kern)
+
+
 def test_meeting_cap_truncation(kern):
     inst = I.make_instance("noisy12", 12, 6, 3, 2, 0.25, 0.25, prior=0.3, seed=3)
     gpu, orc = compare(inst, 2000 * 30, 2000, 2, 6, seed=9, max_steps=8, hist_width=1, **kern)
