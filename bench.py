@@ -1,12 +1,14 @@
 """Benchmark: coupled Gibbs updates per second of the unbiased MCPD hot path.
 
-One step = one full fixed-budget run (mcpd_run_unbiased) of the paper-shaped
-workload: 1298 clones, 97 pools, degree 5, 3 positives, fp 0.05, fn 0.10,
-q = 3/1298, budget 2^28 progress units over 65536 slots (B = 4096), window
-k = 131, l = 1298 (one sweep), score weights.  The instance tables are
+One step = one full fixed-budget run (mcpd_run_unbiased_dev) of the
+paper-shaped workload: 1298 clones, 97 pools, degree 5, 3 positives, fp 0.05,
+fn 0.10, q = 3/1298, budget 2^28 progress units over 65536 slots (B = 4096),
+window k = 131, l = 1298 (one sweep), score weights.  The instance tables are
 resident in device memory before the timed region; every step runs the
-sampler kernel, the integer bucket reduction and the final FP64 division,
-with a new seed per step.
+sampler kernel, the integer bucket reduction and the final FP64 division on
+the device, with a new seed per step, and leaves the marginals, standard
+errors and histogram in device memory.  The same runs with host outputs
+(mcpd_run_unbiased, PCIe-inclusive) are reported beside it.
 
 Also reported on the same line: the batched workloads (128-instance noise
 sweep, 256-instance uneven batch uncapped and with the paper's meeting cap
@@ -195,23 +197,47 @@ def main():
     from paper_2608_30239_amd import instances as I
     from paper_2608_30239_amd import native as N
 
+    import torch
+
     inst, rp = I.paper_shaped()
     d_mean = float(inst.degrees().mean())
     dec = N.Decoder(inst)
+    # outputs stay in device memory (mcpd_run_unbiased_dev): the timed steps
+    # move no marginals over PCIe; only the run's counters come back
+    marg = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    se = torch.empty(inst.n, dtype=torch.float64, device="cuda")
+    hist = torch.empty(64, dtype=torch.int64, device="cuda")
+
+    def step(seed):
+        return dec.run_dev(rp.budget, rp.slots, rp.k, rp.m, seed, marg.data_ptr(), se.data_ptr(), hist.data_ptr(),
+                           hist_bins=64)
+
     for i in range(args.warmup):
-        dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + 1000 + i)
+        step(rp.seed + 1000 + i)
     units = 0
     kernel_ms = []
     site_updates = 0
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + i)
-        units += r["stats"]["progress_units"]
-        site_updates += r["stats"]["single_site_updates"]
-        kernel_ms.append(r["stats"]["kernel_ms"])
+        st = step(rp.seed + i)
+        units += st["progress_units"]
+        site_updates += st["single_site_updates"]
+        kernel_ms.append(st["kernel_ms"])
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the same runs with host outputs (mcpd_run_unbiased): integer sums copied
+    # back and divided on the host, so this rate includes the PCIe transfer
+    host_steps = max(1, min(args.steps, 10))
+    host_units = 0
+    dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + 2000)   # warm-up of the host-output path
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(host_steps):
+        host_units += dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + i)["stats"]["progress_units"]
+    torch.cuda.synchronize()
+    dt_host = time.perf_counter() - t1
     dec.close()
-    st = r["stats"]
     kernel_name = {1: "sampler_kernel (one slot per lane)",
                    2: f"coop_kernel (one slot per {st['group_lanes']} lanes drawing speculatively)"}[st["kernel"]]
     kernel_name += (f", {st['wg_per_cu']} workgroups of 256 lanes per CU, chain state "
@@ -255,6 +281,9 @@ def main():
         "kernel_ms_median": sorted(kernel_ms)[len(kernel_ms) // 2],
         "kernel_updates_per_s": units_per_launch / avg_kernel_s,
         "single_site_updates_per_s": site_updates / dt,
+        "host_outputs": {"updates_per_s": host_units / dt_host, "ms_per_step": dt_host / host_steps * 1e3,
+                         "steps": host_steps, "note": "marginals, SE and histogram returned to host memory "
+                                                       "(PCIe-inclusive); not the value"},
         "roofline": roofline,
     }
     if not args.no_batches:
