@@ -33,9 +33,12 @@ def close(a, b, rel):
     assert np.max(np.abs(a - b)) <= rel * scale
 
 
-def test_device_outputs_equal_host_outputs(kern):
+@pytest.mark.parametrize("full", [False, True], ids=["4096-slots", "benchmark-size"])
+def test_device_outputs_equal_host_outputs(kern, full):
+    """Also at the benchmark's size (2^28 updates over 65536 slots), the
+    configuration whose device-output runs the benchmark times."""
     inst, rp = I.paper_shaped()
-    budget, slots = 4096 * 4096, 4096
+    budget, slots = (rp.budget, rp.slots) if full else (4096 * 4096, 4096)
     dec = N.Decoder(inst)
     try:
         host = dec.run(budget, slots, rp.k, rp.m, 21, **kern)
