@@ -81,6 +81,7 @@ struct InstDesc {
     uint32_t capmax;        // draws after which an unmet pair stops
     uint32_t P;             // slots
     uint32_t p0;            // global index of the first slot (random-number counter)
+    uint32_t slot_q;        // slots per counter: counter x hands out [x q, min((x+1) q, P))
     uint32_t k, ell, W;     // window
     uint32_t cmin;          // max(ell, 1): cost of the cheapest replication
     uint32_t g;             // instance id in the random-number counter
@@ -97,7 +98,7 @@ struct InstDesc {
     uint64_t *S2;           // [nbuckets * n * 3]: limbs of the 128-bit sums of squares
     uint64_t *hist;         // [hist_bins]
     uint64_t *stats;        // [ST_COUNT]
-    uint32_t *next_slot;    // slot counter
+    uint32_t *next_slot;    // [XCDS * SLOT_CTR_STRIDE]: slot counters, one per XCD
     uint32_t *slot_nstar;   // [P] or null
     uint64_t *slot_units;   // [P] or null
 };
@@ -106,6 +107,10 @@ struct InstDesc {
 // XCDs of the device: workgroup i of a launch runs on XCD i mod XCDS, and
 // each XCD has its own L2.
 constexpr uint32_t XCDS = 8;
+// An instance's slots are split into one contiguous range per XCD, each with
+// its own counter in a cache line of its own (SLOT_CTR_STRIDE 32-bit words
+// apart), so that taking a slot is not an atomic on one hot address.
+constexpr uint32_t SLOT_CTR_STRIDE = 32;
 
 struct LaunchArgs {
     const InstDesc *inst;

@@ -41,6 +41,9 @@ namespace host {
 // Control words at the head of the output block: [1] error flags, then one
 // ticket counter per XCD queue (u32 each).
 constexpr size_t CTRL_WORDS = (2 + XCDS + 1) / 2;
+// 64-bit words of an instance's slot counters at the start of its block
+// (block starts aligned to a 128-byte line)
+constexpr size_t SLOT_WORDS = XCDS * SLOT_CTR_STRIDE / 2;
 
 
 thread_local std::string g_last_error;
@@ -397,7 +400,7 @@ bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t bud
 // histogram, S1, S2.
 size_t block_words(size_t n, size_t nb, uint32_t hist_bins)
 {
-    return 1 + ST_COUNT + hist_bins + nb * n + 3 * nb * n;
+    return SLOT_WORDS + ST_COUNT + hist_bins + nb * n + 3 * nb * n;
 }
 
 struct Launch {
@@ -653,6 +656,7 @@ int plan(Launch &L, const Config &c)
         d.hist_width = o.hist_width ? o.hist_width : (uint32_t)I->n;
         d.qthr = (uint32_t)std::floor(std::ldexp(I->q, 32));   // q < 1: below 2^32
         d.p0 = o.first_slot;
+        d.slot_q = (d.P + XCDS - 1) / XCDS;
         d.nbuckets = (uint32_t)std::max<uint64_t>(1, d.B / d.cmin);
         d.place = lay.place;
         d.lds_hist = lay.lds_hist;
@@ -669,6 +673,7 @@ int plan(Launch &L, const Config &c)
         L.coop = c.coop;
         L.acc_stride = std::max<uint32_t>(L.acc_stride, (uint32_t)I->n);
         L.nb[i] = d.nbuckets;
+        words = (words + 15) & ~(size_t)15;
         L.off[i] = words;
         words += block_words((size_t)I->n, d.nbuckets, o.hist_bins);
         L.slot_off[i] = slots_total;
@@ -762,10 +767,10 @@ int plan(Launch &L, const Config &c)
         InstDesc &d = L.desc[i];
         uint64_t *blk = L.d_zero + L.off[i];
         d.next_slot = reinterpret_cast<uint32_t *>(blk);
-        d.stats = blk + 1;
-        d.hist = blk + 1 + ST_COUNT;
-        d.S1 = reinterpret_cast<int64_t *>(blk + 1 + ST_COUNT + o.hist_bins);
-        d.S2 = blk + 1 + ST_COUNT + o.hist_bins + (size_t)d.nbuckets * d.n;
+        d.stats = blk + SLOT_WORDS;
+        d.hist = blk + SLOT_WORDS + ST_COUNT;
+        d.S1 = reinterpret_cast<int64_t *>(blk + SLOT_WORDS + ST_COUNT + o.hist_bins);
+        d.S2 = blk + SLOT_WORDS + ST_COUNT + o.hist_bins + (size_t)d.nbuckets * d.n;
         d.slot_nstar = L.slot_records ? L.d_slot_nstar + L.slot_off[i] : nullptr;
         d.slot_units = L.slot_records ? L.d_slot_units + L.slot_off[i] : nullptr;
     }
@@ -818,14 +823,14 @@ int enqueue(Launch &L, bool timed)
         const InstDesc &d = L.desc[0];
         const size_t n = (size_t)d.n, nb = L.nb[0];
         const uint64_t *blk = L.d_zero + L.off[0];
-        const uint64_t *h = blk + 1 + ST_COUNT;
+        const uint64_t *h = blk + SLOT_WORDS + ST_COUNT;
         const int64_t *S1 = reinterpret_cast<const int64_t *>(h + L.opts.hist_bins);
         const uint64_t *S2 = h + L.opts.hist_bins + nb * n;
         e = launch_finish(S1, S2, (uint32_t)n, (uint32_t)nb, d.P, d.W, L.dev_marginals, L.dev_stderr, L.stream);
         if (e != hipSuccess) return hip_fail((hipError_t)e, "finish launch");
         if (L.dev_hist)
             HIP_TRY(hipMemcpyAsync(L.dev_hist, h, L.opts.hist_bins * 8, hipMemcpyDeviceToDevice, L.stream));
-        HIP_TRY(hipMemcpyAsync(L.h_out, L.d_zero, (L.off[0] + 1 + ST_COUNT + L.opts.hist_bins) * 8,
+        HIP_TRY(hipMemcpyAsync(L.h_out, L.d_zero, (L.off[0] + SLOT_WORDS + ST_COUNT + L.opts.hist_bins) * 8,
                                hipMemcpyDeviceToHost, L.stream));
     } else {
         HIP_TRY(hipMemcpyAsync(L.h_out, L.d_zero, L.zero_words * 8, hipMemcpyDeviceToHost, L.stream));
@@ -879,8 +884,8 @@ int finish_item(const Launch &L, size_t i, double *marginals, double *stderr_out
     const size_t n = (size_t)d.n;
     const uint32_t nb = L.nb[i];
     const uint64_t *blk = L.h_out + L.off[i];
-    const uint64_t *st = blk + 1;
-    const uint64_t *h = blk + 1 + ST_COUNT;
+    const uint64_t *st = blk + SLOT_WORDS;
+    const uint64_t *h = blk + SLOT_WORDS + ST_COUNT;
     const int64_t *S1 = reinterpret_cast<const int64_t *>(h + L.opts.hist_bins);
     const uint64_t *S2 = h + L.opts.hist_bins + (size_t)nb * n;
     const uint32_t slots = d.P;
@@ -944,8 +949,8 @@ int copy_buckets(const Launch &L, size_t i, uint32_t rows, int64_t *sum, uint64_
     const size_t n = (size_t)d.n;
     const uint32_t nb = L.nb[i];
     const uint64_t *blk = L.h_out + L.off[i];
-    if (blk[1 + ST_NSTAR_MAX] > rows) return fail(MCPD_EINVAL, "bucket_rows below N*");
-    const uint64_t *h = blk + 1 + ST_COUNT;
+    if (blk[SLOT_WORDS + ST_NSTAR_MAX] > rows) return fail(MCPD_EINVAL, "bucket_rows below N*");
+    const uint64_t *h = blk + SLOT_WORDS + ST_COUNT;
     const size_t r = std::min<size_t>(rows, nb);
     if (sum) {
         std::memset(sum, 0, sizeof(int64_t) * (size_t)rows * n);

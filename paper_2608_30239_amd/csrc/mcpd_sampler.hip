@@ -548,6 +548,39 @@ __device__ __forceinline__ void copy_to_lds(uint32_t *dst, const void *src, uint
 // One workgroup's share of one instance: place the tables (and state) in
 // LDS, let every lane take slots until the instance has none left, then add
 // the lanes' statistics and the histogram to the instance's totals.
+// A slot of instance D for this workgroup: from its XCD's range first (one
+// atomic add), then, checking before adding, from the other ranges in turn.
+// Returns P when every range is used up.  Counters only grow, so every
+// workgroup eventually sees them all used up.
+__device__ __forceinline__ uint32_t take_slot(DescPtr D)
+{
+    const uint32_t home = blockIdx.x % XCDS, q = D->slot_q, P = D->P;
+    for (uint32_t i = 0; i < XCDS; ++i) {
+        const uint32_t x = (home + i) % XCDS;
+        const uint32_t lo = x * q;
+        if (lo >= P) continue;
+        const uint32_t n = min(q, P - lo);
+        uint32_t *c = D->next_slot + x * SLOT_CTR_STRIDE;
+        if (i != 0 && __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n) continue;
+        const uint32_t k = atomicAdd(c, 1u);
+        if (k < n) return lo + k;
+    }
+    return P;
+}
+
+// Whether instance d has a slot left in any range.
+__device__ __forceinline__ bool slots_left(const InstDesc *d)
+{
+    for (uint32_t x = 0; x < XCDS; ++x) {
+        const uint32_t lo = x * d->slot_q;
+        if (lo >= d->P) break;
+        const uint32_t n = min(d->slot_q, d->P - lo);
+        if (__hip_atomic_load(d->next_slot + x * SLOT_CTR_STRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n)
+            return true;
+    }
+    return false;
+}
+
 template <bool SL, bool TL, int F>
 __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_t *smem, uint32_t k0, uint32_t k1)
 {
@@ -598,7 +631,6 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_
     for (int e = 0; e < CACHE; ++e) { s.ctag[e] = NO_TAG; s.cval[e] = 0; }
     const uint32_t P = D->P;
     const uint32_t g = D->g;
-    uint32_t *next_slot = D->next_slot;
 
     // Pipeline registers: the random block of the current pair of draws
     // (t, t+1) and the site and row of draw t, fetched one draw ahead.
@@ -611,7 +643,7 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_
     for (;;) {
         if (s.mode != MODE_RUN) {
             if (s.mode == MODE_NEED_SLOT) {
-                const uint32_t p = atomicAdd(next_slot, 1u);
+                const uint32_t p = take_slot(D);
                 if (p >= P) {
                     s.mode = MODE_DONE;
                 } else {
@@ -732,8 +764,7 @@ __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
             const uint32_t it = take_ticket(a);
             uint32_t skip = 1;
             if (it < a.nticket) {
-                const InstDesc *d = a.inst + a.tickets[it];
-                skip = __hip_atomic_load(d->next_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= d->P;
+                skip = !slots_left(a.inst + a.tickets[it]);
             }
             sh_item = it;
             sh_skip = skip;
@@ -1278,7 +1309,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
         if (!__all(s.mode == MODE_RUN)) {
             if (s.mode == MODE_NEED_SLOT) {
                 uint32_t p = 0;
-                if (C.gl == 0) p = atomicAdd(D->next_slot, 1u);
+                if (C.gl == 0) p = take_slot(D);
                 p = __shfl(p, (int)C.leader);
                 if (p >= P) {
                     s.mode = MODE_DONE;
@@ -1388,8 +1419,7 @@ __global__ void __launch_bounds__(256, coop_waves_per_simd(F)) coop_kernel(Launc
             const uint32_t it = take_ticket(a);
             uint32_t skip = 1;
             if (it < a.nticket) {
-                const InstDesc *d = a.inst + a.tickets[it];
-                skip = __hip_atomic_load(d->next_slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= d->P;
+                skip = !slots_left(a.inst + a.tickets[it]);
             }
             sh_item = it;
             sh_skip = skip;
