@@ -142,7 +142,9 @@ typedef struct mcpd_run_stats {
                                      (their numerators were flushed by a scan)  */
     uint64_t lanes;               /* persistent lanes of the launch             */
     uint32_t placement;           /* bit 0: chain state in LDS; bit 1: tables in
-                                     LDS; bit 2: cooperative kernel             */
+                                     LDS; bit 2: cooperative kernel; bit 3:
+                                     threshold table alone in LDS (alias table
+                                     and rows in global memory)                 */
     uint32_t wg_per_cu;           /* workgroups per CU of the launch            */
     uint32_t wg_slots;            /* slots a workgroup runs at once for this
                                      instance: 256 lanes (fewer in a narrow

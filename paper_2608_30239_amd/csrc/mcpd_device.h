@@ -49,7 +49,11 @@ __host__ __device__ constexpr int fmt_row_bytes(int f)
 // Lanes per workgroup; also the stride of the lane-fastest state layout.
 constexpr uint32_t WG_LANES = 256;
 
-enum Place : uint32_t { PLACE_STATE_LDS = 1, PLACE_TABLES_LDS = 2, PLACE_COOP = 4 };
+enum Place : uint32_t { PLACE_STATE_LDS = 1, PLACE_TABLES_LDS = 2, PLACE_COOP = 4, PLACE_THR_LDS = 8 };
+// PLACE_THR_LDS: the cooperative kernel keeps the threshold table in LDS
+// while the alias table and rows stay in global memory (rows of up to 8
+// entries, at most 511 thresholds), so a draw waits on two global reads
+// instead of three.
 
 // Wavefronts of a workgroup of the cooperative kernel.
 constexpr uint32_t COOP_WAVES_PER_WG = WG_LANES / 64;

@@ -386,11 +386,14 @@ bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t bud
     const bool tl = (plan == 0 || plan == 1) && pat + hist + L.tab_bytes + states <= budget;
     if (plan == 1 && !tl) return false;
     if (pat + hist + states > budget) return false;
+    // the thresholds alone, when the other tables stay in global memory
+    const size_t thr = align16((size_t)I->thr_len * 8u);
+    const bool thr_lds = !tl && plan == 0 && fmt_entries(fmt) <= 8 && pat + hist + thr + states <= budget;
     L.lanes = (uint32_t)groups;
-    L.place = PLACE_STATE_LDS | PLACE_COOP | (tl ? PLACE_TABLES_LDS : 0u);
+    L.place = PLACE_STATE_LDS | PLACE_COOP | (tl ? PLACE_TABLES_LDS : 0u) | (thr_lds ? PLACE_THR_LDS : 0u);
     L.lds_hist = (uint32_t)(pat / 4);
     L.lds_tab = (uint32_t)((pat + hist) / 4);
-    L.lds_state = L.lds_tab + (tl ? L.tab_bytes / 4 : 0u);
+    L.lds_state = L.lds_tab + (tl ? L.tab_bytes / 4 : thr_lds ? (uint32_t)(thr / 4) : 0u);
     L.wave_words = (uint32_t)ww;
     L.used = (size_t)L.lds_state * 4 + states;
     return true;

@@ -1271,6 +1271,13 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
         copy_to_lds(tab + D->tab_off_alias / 4, D->alias, 1u << D->abits);
         copy_to_lds(tab + D->tab_off_rows / 4, D->rows, (uint32_t)D->n * D->row_bytes / 4u);
     }
+    const uint64_t *thr = D->thr;
+    if (TL) {
+        thr = reinterpret_cast<const uint64_t *>(tab + D->tab_off_thr / 4);
+    } else if (D->place & PLACE_THR_LDS) {
+        copy_to_lds(tab, D->thr, D->thr_len * 2u);
+        thr = reinterpret_cast<const uint64_t *>(tab);
+    }
     const uint32_t gl = lane & (gsz - 1u);
     Coop<TL, F> C{a,
                   D,
@@ -1279,7 +1286,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                   nullptr,
                   nullptr,
                   reinterpret_cast<const uint8_t *>(smem),
-                  TL ? reinterpret_cast<const uint64_t *>(tab + D->tab_off_thr / 4) : D->thr,
+                  thr,
                   TL ? tab + D->tab_off_alias / 4 : D->alias,
                   TL ? tab + D->tab_off_rows / 4 : D->rows,
                   gl,
