@@ -399,7 +399,7 @@ bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t bud
     return true;
 }
 
-// Words of one instance's block of outputs: slot counter, statistics,
+// Words of one instance's block of outputs: slot counters, statistics,
 // histogram, S1, S2.
 size_t block_words(size_t n, size_t nb, uint32_t hist_bins)
 {

@@ -725,10 +725,6 @@ __device__ __forceinline__ void run_item(const LaunchArgs &a, DescPtr D, uint32_
     __syncthreads();
 }
 
-// Persistent kernel over a batch: a workgroup takes tickets until the queue
-// is empty.  Every workgroup leaves when the ticket counter passes the end,
-// and every lane leaves an instance when its slot counter passes P, so the
-// grid always drains.
 // The next ticket of this workgroup: tickets come in one queue per XCD
 // (instances spread over the queues by work, so that the workgroups of one
 // XCD share few instances' tables in their L2); a workgroup takes from the
@@ -749,6 +745,10 @@ __device__ __forceinline__ uint32_t take_ticket(const LaunchArgs &a)
     return a.nticket;
 }
 
+// Persistent kernel over a batch: a workgroup takes tickets until the queues
+// are empty.  Every workgroup leaves when every ticket queue is used up, and
+// every lane leaves an instance when every range of its slots is used up, so
+// the grid always drains.
 template <int F>
 __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
 {
