@@ -77,6 +77,30 @@ def test_one_byte_rows_with_padding(degree, kern):
     compare(inst, 256 * 3 * 400, 256, 41, 400, seed=13, init_mode=1, **kern)
 
 
+def test_one_decoder_through_changing_shapes():
+    """One decoder (its launch plan, workspace and output block reused) through
+    runs whose shapes change: slot counts that are and are not multiples of
+    the per-XCD slot ranges, fewer slots than ranges, one slot, both kernels
+    and several group sizes, both initial distributions, an empty window;
+    every run against the oracle."""
+    inst, _ = I.tiny_plain()
+    runs = [(4096 * 120, 4096, 10, 50, dict()),
+            (7 * 200, 7, 10, 50, dict(kernel=2, group_lanes=8)),
+            (1 * 300, 1, 3, 30, dict(kernel=1)),
+            (1000 * 130, 1000, 0, 0, dict(kernel=2, group_lanes=64, init_mode=1)),
+            (8191 * 55, 8191, 5, 20, dict(kernel=2, group_lanes=16)),
+            (333 * 400, 333, 10, 50, dict(kernel=1, init_mode=1)),
+            (4096 * 120, 4096, 10, 50, dict())]
+    dec = N.Decoder(inst)
+    try:
+        for i, (budget, slots, k, m, opt) in enumerate(runs):
+            orc, nb = P.oracle_run(inst, budget, slots, k, m, seed=40 + i, **opt)
+            gpu = dec.run(budget, slots, k, m, 40 + i, slot_records=True, buckets=nb, **opt)
+            P.check(gpu, orc, budget, slots, m)
+    finally:
+        dec.close()
+
+
 def test_meeting_cap_truncation(kern):
     inst = I.make_instance("noisy12", 12, 6, 3, 2, 0.25, 0.25, prior=0.3, seed=3)
     gpu, orc = compare(inst, 2000 * 30, 2000, 2, 6, seed=9, max_steps=8, hist_width=1, **kern)
