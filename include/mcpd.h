@@ -297,9 +297,10 @@ int mcpd_batch_create(mcpd_instance *const *insts, int32_t count, const uint64_t
 int mcpd_batch_run(mcpd_batch *batch, uint64_t seed, double *const *marginals,
                    double *const *stderr_out, uint64_t *const *hist, mcpd_run_stats *stats);
 
-/* Autotuner: run the batch once per candidate launch shape (kernel x
- * workgroups per CU x slots per ticket x LDS layout, within opts' fixed
- * values), time the sampler, keep the fastest.  Lane kernel layouts: wide
+/* Autotuner: run the batch twice (seeds seed and seed + 1) per candidate
+ * launch shape (kernel x workgroups per CU x slots per ticket x LDS layout,
+ * within opts' fixed values), time the sampler, keep the fastest mean (the
+ * entries' ms is that mean).  Lane kernel layouts: wide
  * only (chain state in LDS for 256 lanes when it fits, else in global
  * memory), or also narrow (a workgroup runs only as many lanes as fit the
  * state in LDS, at least 8); cooperative kernel: one state per group of 8,

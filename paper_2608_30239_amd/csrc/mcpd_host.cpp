@@ -1373,8 +1373,12 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
         int rc = plan(L, c);
         if (rc == MCPD_ENOMEM) continue;   // too much numerator workspace at this width
         if (rc) return rc;
+        // two runs (seeds seed and seed + 1), so that one run's longest pair
+        // does not decide between close candidates
         if ((rc = execute(L, seed, false))) return rc;
-        const double ms = L.last_ms;
+        double ms = L.last_ms;
+        if ((rc = execute(L, seed + 1, false))) return rc;
+        ms = 0.5 * (ms + L.last_ms);
         if (entries && done < cap)
             entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, c.narrow, c.coop ? 2u : 1u, c.coop ? 1u << c.group_log2 : 1u, 0u, ms};
         ++done;
