@@ -83,11 +83,13 @@ def cpu_baseline(inst, rp, threads: int, min_seconds: float = 10.0, max_runs: in
         t0 = time.perf_counter()
         r = M.run(rp.budget, rp.slots, rp.k, rp.m, seed=rp.seed + runs, nthreads=threads)
         dt += time.perf_counter() - t0
-        units += r["stats"]["retained_units"] + r["stats"]["discarded_units"]
+        units += r["stats"]["retained_units"]
         runs += 1
     return dict(value=units / dt, unit="coupled Gibbs updates/s", cores=threads, kind="oracle",
+                seconds_per_run=dt / runs,
                 sample=f"{runs} whole runs of the workload ({rp.slots} slots, budget {rp.budget}); "
-                       f"{units} coupled updates in {dt:.2f} s")
+                       f"{units} retained coupled updates in {dt:.2f} s (the oracle also runs the "
+                       f"replications it discards to their end; they are not counted)")
 
 
 def cpu_baseline_one_thread(inst, rp, slots: int = 4096, min_seconds: float = 3.0):
@@ -102,11 +104,11 @@ def cpu_baseline_one_thread(inst, rp, slots: int = 4096, min_seconds: float = 3.
         t0 = time.perf_counter()
         r = M.run(B * slots, slots, rp.k, rp.m, seed=rp.seed + runs, nthreads=1)
         dt += time.perf_counter() - t0
-        units += r["stats"]["retained_units"] + r["stats"]["discarded_units"]
+        units += r["stats"]["retained_units"]
         runs += 1
     return dict(value=units / dt, unit="coupled Gibbs updates/s", cores=1, kind="oracle",
                 sample=f"{runs} runs of the first {slots} slots of the workload (B = {B}); "
-                       f"{units} coupled updates in {dt:.2f} s")
+                       f"{units} retained coupled updates in {dt:.2f} s")
 
 
 def batch_lines(steps: int):
@@ -132,7 +134,7 @@ def batch_lines(steps: int):
             for s in range(steps):
                 r = bt.run(s, outputs=False)
                 ms.append(r[0]["stats"]["kernel_ms"])
-                units += sum(x["stats"]["progress_units"] for x in r)
+                units += sum(x["stats"]["retained_units"] for x in r)
             cfg = bt.config()
             out[name] = dict(instances=len(insts), graph_ms=sum(ms) / len(ms),
                              updates_per_s=units / (sum(ms) / 1e3), kernel=r[0]["stats"]["kernel"],
@@ -214,14 +216,21 @@ def main():
 
     for i in range(args.warmup):
         step(rp.seed + 1000 + i)
+    # value counts the method's updates: the draws of retained replications.
+    # A replication that can no longer be retained is stopped and its draws
+    # are replayed negated; those draws are counted apart (rollback_units).
     units = 0
+    progress = 0
+    rollback = 0
     kernel_ms = []
     site_updates = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         st = step(rp.seed + i)
-        units += st["progress_units"]
+        units += st["retained_units"]
+        progress += st["progress_units"]
+        rollback += st["rollback_units"]
         site_updates += st["single_site_updates"]
         kernel_ms.append(st["kernel_ms"])
     torch.cuda.synchronize()
@@ -234,7 +243,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for i in range(host_steps):
-        host_units += dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + i)["stats"]["progress_units"]
+        host_units += dec.run(rp.budget, rp.slots, rp.k, rp.m, rp.seed + i)["stats"]["retained_units"]
     torch.cuda.synchronize()
     dt_host = time.perf_counter() - t1
     dec.close()
@@ -281,6 +290,10 @@ def main():
         "kernel_ms_median": sorted(kernel_ms)[len(kernel_ms) // 2],
         "kernel_updates_per_s": units_per_launch / avg_kernel_s,
         "single_site_updates_per_s": site_updates / dt,
+        "progress_units_per_s": progress / dt,
+        "rollback_units_per_run": rollback / args.steps,
+        "note_units": "value counts retained replications' draws; progress units add the draws of "
+                      "replications stopped once they could no longer be retained, and their replay",
         "host_outputs": {"updates_per_s": host_units / dt_host, "ms_per_step": dt_host / host_steps * 1e3,
                          "steps": host_steps, "note": "marginals, SE and histogram returned to host memory "
                                                        "(PCIe-inclusive); not the value"},

@@ -1,9 +1,10 @@
 // Persistent slot-refill sampler for unbiased Markov chain pool decoding on
 // gfx950.
 //
-// One lane owns one logical slot at a time (Algorithm 4: "the GPU scheduler
-// maps a logical slot p to one persistent thread") and runs its i.i.d.
-// coupled replications (Algorithm 3) one after the other.  Slots are handed
+// One lane (lane kernel) or one group of lanes (cooperative kernel) owns one
+// logical slot at a time and runs its i.i.d. coupled replications
+// (Algorithm 3) one after the other, as the fixed-budget scheduler of
+// Algorithm 4 prescribes for a persistent worker.  Slots are handed
 // out dynamically from a per-instance counter; the result does not depend on
 // which lane runs which slot because every random number is keyed by
 // (instance, slot, replication, draw).

@@ -217,10 +217,10 @@ def test_noise_sweep_full_size_every_instance():
         P.check(outs[0][i], orc, budget, slots, m)
 
 
-def test_uneven_batch_full_size_sampled_instances():
-    """256 uneven instances (n in [200, 20000]) in one launch; every 16th
-    instance and the largest are checked in full against the oracle, every
-    instance against the invariants of its slot records."""
+def test_uneven_batch_full_size_every_instance():
+    """256 uneven instances (n in [200, 20000]) in one launch at full size:
+    every instance in full against the oracle, and against the invariants
+    of its slot records."""
     insts, params = I.uneven_batch()
     spec = [(x, p.budget, p.slots, p.k, p.m) for x, p in zip(insts, params)]
     outs, cfg = run_batch(spec, seed=0, keep_slot_records=1)
@@ -235,8 +235,22 @@ def test_uneven_batch_full_size_sampled_instances():
         over = res[i]["slot_units"] > B
         assert int(over.sum()) == st["zero_completion_slots"]
         assert int(res[i]["hist"].sum()) + st["cap_hits"] == st["reps_retained"]
-    largest = int(np.argmax([x.n for x in insts]))
-    for i in sorted(set(range(0, len(spec), 16)) | {largest}):
-        inst, budget, slots, k, m = spec[i]
+    for i, (inst, budget, slots, k, m) in enumerate(spec):
+        print(f"[oracle] uneven instance {i}: n={inst.n} m={inst.m} slots={slots}", flush=True)
         orc, _ = P.oracle_run(inst, budget, slots, k, m, seed=0, instance_id=i)
+        P.check(res[i], orc, budget, slots, m)
+
+
+def test_uneven_batch_capped_every_instance():
+    """The same batch with the paper's meeting cap of 20 sweeps per instance
+    (cap_sweeps = 20): pairs stopped by the cap keep the truncated estimator,
+    every instance in full against the oracle run with that cap."""
+    insts, params = I.uneven_batch()
+    spec = [(x, p.budget, p.slots, p.k, p.m) for x, p in zip(insts, params)]
+    outs, cfg = run_batch(spec, seed=1, keep_slot_records=1, cap_sweeps=20)
+    res = outs[0]
+    assert sum(r["stats"]["cap_hits"] for r in res) > 0
+    for i, (inst, budget, slots, k, m) in enumerate(spec):
+        print(f"[oracle] capped uneven instance {i}: n={inst.n} m={inst.m} slots={slots}", flush=True)
+        orc, _ = P.oracle_run(inst, budget, slots, k, m, seed=1, instance_id=i, max_steps=20 * inst.n)
         P.check(res[i], orc, budget, slots, m)

@@ -54,6 +54,8 @@ def test_device_outputs_equal_host_outputs(kern, full):
     orc, _ = P.oracle_run(inst, budget, slots, rp.k, rp.m, seed=21)
     close(marg, orc["marginals"], 1e-12)
     close(se, orc["stderr"], 1e-10)
+    # clone by clone against the value the (bit-identical) integer sums define
+    P.check_elementwise(dict(marginals=marg, stderr=se), orc, slots)
 
 
 def test_device_outputs_optional_parts_and_one_slot():

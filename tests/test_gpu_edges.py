@@ -104,3 +104,41 @@ def test_largest_clone_count(n, opt):
         assert not (gpu["stats"]["placement"] & 1)      # state in global memory
     else:
         assert gpu["stats"]["placement"] & 4
+
+
+def test_strict_cap_reports_mcpd_ecap(kern):
+    """strict_cap: a run in which a retained pair hits the meeting cap
+    returns MCPD_ECAP; the same run without it returns the capped estimate,
+    which matches the oracle's truncated one."""
+    inst, rp = I.tiny_plain()
+    cap = rp.m   # the smallest cap allowed: max(m, 1) draws
+    gpu, orc = compare(inst, 2048 * 3 * rp.m, 2048, rp.k, rp.m, seed=11, max_steps=cap, **kern)
+    assert gpu["stats"]["cap_hits"] > 0 and orc["stats"]["cap_hits"] == gpu["stats"]["cap_hits"]
+    dec = N.Decoder(inst)
+    try:
+        with pytest.raises(N.McpdError) as e:
+            dec.run(2048 * 3 * rp.m, 2048, rp.k, rp.m, 11, max_steps=cap, strict_cap=1, **kern)
+        assert e.value.code == N.MCPD_ECAP
+        # no pair reaches a cap of 2^32 - 1 draws: strict mode returns normally
+        ok = dec.run(2048 * 3 * rp.m, 2048, rp.k, rp.m, 11, strict_cap=1, **kern)
+        assert ok["stats"]["cap_hits"] == 0
+    finally:
+        dec.close()
+
+
+def test_numerator_workspace_limit_reports_mcpd_enomem():
+    """The lane kernel's dense numerator rows (lanes x n x 8 bytes) are
+    capped at 64 GiB: 2^17 clones at two workgroups of 256 lanes per CU
+    would need 128 GiB, so the run returns MCPD_ENOMEM before allocating
+    anything, and the instance still runs at one workgroup per CU."""
+    n = 1 << 17
+    inst = I.make_instance(f"n{n}", n, 8000, 3, 8, 0.05, 0.1, prior=8 / n, seed=3)
+    dec = N.Decoder(inst)
+    try:
+        with pytest.raises(N.McpdError) as e:
+            dec.run(256 * n, 256, n // 10 + 1, n, 10, kernel=1, wg_per_cu=2)
+        assert e.value.code == N.MCPD_ENOMEM
+        ok = dec.run(256 * n, 256, n // 10 + 1, n, 10, kernel=1, wg_per_cu=1)
+        assert ok["stats"]["reps_retained"] == 256
+    finally:
+        dec.close()
