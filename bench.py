@@ -31,28 +31,72 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X unit counts and clock: 256 CUs x 4 SIMDs x 16 lanes, 2.4 GHz.
-CUS, SIMDS, LANES, CLOCK = 256, 4, 16, 2.4e9
-# Peak 32-bit VALU issue: one lane-op per lane per clock (no packed ops).
-ALU_PEAK_OPS = CUS * SIMDS * LANES * CLOCK              # 3.93e13 lane-ops/s
-# LDS: 128 bytes per clock per CU.
-LDS_PEAK_BPS = CUS * 128 * CLOCK                        # 7.86e13 B/s
-
-
-def alg_ops_per_update(d: float) -> float:
-    """Algorithmic 32-bit lane-op slots of one coupled update (after meeting,
-    which is where the chains spend almost all draws): half a Philox4x32-10
-    block (10 rounds x (2 quarter-rate 32x32->64 products = 8 slots + 2
-    three-input xors)) = 50, the alias site draw (shift, mask, compare,
-    select) = 4, the free test and pattern step of each of the d pools = 4d,
-    the threshold index and 53-bit comparison = 4."""
-    return 50.0 + 4.0 + 4.0 * d + 4.0
+# Iterations of each peak-rate probe (about 10-30 ms of device time each).
+PROBE_ITERS = {"lds_b32": 40000, "lds_b64": 20000, "lds_b128": 10000, "lds_b32_random": 20000,
+               "valu_add": 40000, "valu_mul_lo": 10000, "valu_mul_hi": 10000, "valu_bitop3": 40000,
+               "valu_mul64": 10000, "philox10": 20000}
 
 
 def lds_bytes_per_update(d: float) -> float:
-    """Algorithmic LDS bytes of one update: the alias word (4), the clone row
-    (8), one bit word (4) and d count words (4d) of the pair, one threshold (8)."""
-    return 4.0 + 8.0 + 4.0 + 4.0 * d + 8.0
+    """Algorithmic LDS bytes of one coupled update at dword granularity: per
+    pair the bit word holding x_I and y_I (4) and one dword per pool of the
+    drawn clone (4d); shared per instance the alias column (8) and the clone
+    row (8).  20 + 4d = 40 B at degree 5."""
+    return 4.0 + 4.0 * d + 8.0 + 8.0
+
+
+def alg_full_rate_ops(d: float) -> float:
+    """Algorithmic full-rate 32-bit lane operations of one update besides its
+    random numbers: the alias site draw (shift, mask, compare, select) = 4,
+    the free test and pattern step of each of the d pools = 4d, the
+    threshold index and 53-bit comparison = 4."""
+    return 4.0 + 4.0 * d + 4.0
+
+
+def measure_peaks():
+    """Peak rates of the device measured by the library's probes."""
+    from paper_2608_30239_amd import native as N
+    return {k: N.mcpd_probe(k, PROBE_ITERS[k]) for k in N.PROBES}
+
+
+def roofline_of(peaks, d: float, units_per_launch: float, kernel_s: float, kernel_name: str):
+    """Achieved rates of one launch against the measured peaks.
+
+    LDS: algorithmic bytes (lds_bytes_per_update x the launch's retained
+    updates) over the launch's time, against the best streaming LDS read
+    rate the probes measured.  VALU: the algorithmic work of one update is
+    half a Philox4x32-10 block (one block serves two draws) plus
+    alg_full_rate_ops full-rate lane operations; at the measured Philox
+    block rate and 32-bit add rate that bounds the update rate at
+    1 / (0.5 / philox_per_s + ops / add_per_s)."""
+    lds_peak = max(peaks[k]["per_second"] for k in ("lds_b32", "lds_b64", "lds_b128"))
+    best = max(("lds_b32", "lds_b64", "lds_b128"), key=lambda k: peaks[k]["per_second"])
+    lds_ach = lds_bytes_per_update(d) * units_per_launch / kernel_s
+    upd = units_per_launch / kernel_s
+    alu_roof = 1.0 / (0.5 / peaks["philox10"]["per_second"] + alg_full_rate_ops(d) / peaks["valu_add"]["per_second"])
+    return {
+        "bound": "lds",
+        "achieved": lds_ach / 1e12,
+        "peak": lds_peak / 1e12,
+        "unit": "TB/s",
+        "frac": lds_ach / lds_peak,
+        "traffic": measured_traffic(),
+        "kernel": kernel_name,
+        "lds_bytes_per_update": lds_bytes_per_update(d),
+        "lds_peak_probe": best,
+        "lds_peak_bytes_per_cu_per_clock": peaks[best]["per_cu_per_clock"],
+        "alu": {
+            "achieved_updates_per_s": upd,
+            "peak_updates_per_s": alu_roof,
+            "frac": upd / alu_roof,
+            "philox_blocks_per_s": peaks["philox10"]["per_second"],
+            "add_lane_ops_per_s": peaks["valu_add"]["per_second"],
+            "full_rate_ops_per_update": alg_full_rate_ops(d),
+        },
+        "binding": "valu issue (SQ counters: VALU busy is high while LDS runs far below its peak)",
+        "peaks_measured": {k: {"per_cu_per_clock": v["per_cu_per_clock"], "per_second": v["per_second"],
+                               "clock_hz": v["clock_hz"]} for k, v in peaks.items()},
+    }
 
 
 def measured_traffic():
@@ -255,21 +299,7 @@ def main():
     value = units / dt
     avg_kernel_s = sum(kernel_ms) / len(kernel_ms) / 1e3
     units_per_launch = units / args.steps
-    achieved_ops = alg_ops_per_update(d_mean) * units_per_launch / avg_kernel_s
-    roofline = {
-        "bound": "alu",
-        "achieved": achieved_ops / 1e12,
-        "peak": ALU_PEAK_OPS / 1e12,
-        "unit": "Tops/s",
-        "frac": achieved_ops / ALU_PEAK_OPS,
-        "traffic": measured_traffic(),
-        "kernel": kernel_name,
-        "alg_ops_per_update": alg_ops_per_update(d_mean),
-        "lds_bytes_per_update": lds_bytes_per_update(d_mean),
-        "lds_achieved_TBps": lds_bytes_per_update(d_mean) * units_per_launch / avg_kernel_s / 1e12,
-        "lds_peak_TBps": LDS_PEAK_BPS / 1e12,
-        "lds_frac": lds_bytes_per_update(d_mean) * units_per_launch / avg_kernel_s / LDS_PEAK_BPS,
-    }
+    roofline = roofline_of(measure_peaks(), d_mean, units_per_launch, avg_kernel_s, kernel_name)
     out = {
         "metric": "coupled Gibbs updates/s + marginal RMSE per GPU-second (learned vs score weights)",
         "value": value,

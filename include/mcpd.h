@@ -424,6 +424,49 @@ int mcpd_set_learned_weights(mcpd_instance *inst, mcpd_mlp *mlp, double alpha, d
 void mcpd_mlp_destroy(mcpd_mlp *mlp);
 
 /* Static name of an error code. */
+/* ---- Peak-rate probes (measurement support) ----------------------------
+ * The benchmark's roofline divides achieved rates by peaks measured on the
+ * device by these probes, not by figures assumed from other chips.  Each
+ * probe launches eight workgroups of 256 lanes per compute unit that run
+ * `iters` iterations of one kind of independent operation:
+ *   LDS_B32, LDS_B64, LDS_B128: conflict-free streaming LDS reads of 4, 8 or
+ *     16 bytes per lane (the 64 lanes of a read touch consecutive words);
+ *   LDS_B32_RANDOM: 4-byte LDS reads at fixed pseudo-random addresses;
+ *   VALU_ADD, VALU_MUL_LO, VALU_MUL_HI, VALU_BITOP3, VALU_MUL64: 32-bit
+ *     add, low and high 32x32 products, three-input xor, and the full 64-bit
+ *     product of two 32-bit words (one lane operation each);
+ *   PHILOX10: whole Philox4x32-10 blocks as the sampler computes them.
+ * Results: per_second for the whole device (the launch's work over its
+ * event-timed duration), the shader clock the probe ran at (in-kernel clock
+ * counters), per_cu_per_clock = per_second / (clock x compute units) in
+ * bytes, lane operations or blocks, and the kernel time.  Uses the current device; allocates and frees
+ * a few MB.  Errors: MCPD_EINVAL (kind out of range, iters = 0, out null),
+ * MCPD_ENOMEM, MCPD_EDEVICE. */
+enum {
+    MCPD_PROBE_LDS_B32 = 0,
+    MCPD_PROBE_LDS_B64 = 1,
+    MCPD_PROBE_LDS_B128 = 2,
+    MCPD_PROBE_LDS_B32_RANDOM = 3,
+    MCPD_PROBE_VALU_ADD = 4,
+    MCPD_PROBE_VALU_MUL_LO = 5,
+    MCPD_PROBE_VALU_MUL_HI = 6,
+    MCPD_PROBE_VALU_BITOP3 = 7,
+    MCPD_PROBE_VALU_MUL64 = 8,
+    MCPD_PROBE_PHILOX10 = 9,
+    MCPD_PROBE_COUNT = 10
+};
+
+typedef struct mcpd_probe_result {
+    double per_cu_per_clock;
+    double per_second;
+    double clock_hz;
+    double ms;
+    uint32_t cus;
+    uint32_t reserved;
+} mcpd_probe_result;
+
+int mcpd_probe(int kind, uint32_t iters, mcpd_probe_result *out);
+
 const char *mcpd_strerror(int code);
 
 /* Detail of the last error on the calling thread ("" if none). */

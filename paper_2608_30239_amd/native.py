@@ -88,17 +88,27 @@ class TuneEntry(C.Structure):
 
 # Every symbol include/mcpd.h declares.
 EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_prune", "mcpd_create", "mcpd_set_weights",
-           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_run_unbiased_dev", "mcpd_destroy", "mcpd_batch_create",
+           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_run_unbiased_dev",
+           "mcpd_destroy", "mcpd_batch_create",
            "mcpd_batch_run", "mcpd_batch_tune", "mcpd_batch_config", "mcpd_batch_buckets",
            "mcpd_batch_slot_records", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_features",
            "mcpd_mlp_create", "mcpd_mlp_get_params", "mcpd_mlp_set_params", "mcpd_mlp_forward",
            "mcpd_mlp_set_training_rows", "mcpd_mlp_set_training_data", "mcpd_mlp_loss_grad",
-           "mcpd_mlp_train", "mcpd_set_learned_weights", "mcpd_mlp_destroy", "mcpd_strerror",
+           "mcpd_mlp_train", "mcpd_set_learned_weights", "mcpd_mlp_destroy", "mcpd_probe", "mcpd_strerror",
            "mcpd_last_error")
 
 MLP_FEATURES = 8
 MLP_HIDDEN = 64
 MLP_PARAMS = 4801
+
+
+PROBES = ("lds_b32", "lds_b64", "lds_b128", "lds_b32_random", "valu_add", "valu_mul_lo", "valu_mul_hi",
+          "valu_bitop3", "valu_mul64", "philox10")
+
+
+class ProbeResult(C.Structure):
+    _fields_ = [("per_cu_per_clock", C.c_double), ("per_second", C.c_double), ("clock_hz", C.c_double),
+                ("ms", C.c_double), ("cus", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class AdamW(C.Structure):
@@ -158,6 +168,7 @@ def load(path: Optional[str] = None):
         L.mcpd_set_learned_weights.argtypes = [vp, vp, C.c_double, vp]
         L.mcpd_mlp_destroy.argtypes = [vp]
         L.mcpd_mlp_destroy.restype = None
+        L.mcpd_probe.argtypes = [C.c_int, C.c_uint32, C.POINTER(ProbeResult)]
         L.mcpd_strerror.argtypes = [C.c_int]
         L.mcpd_strerror.restype = C.c_char_p
         L.mcpd_last_error.argtypes = []
@@ -360,6 +371,15 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def mcpd_probe(kind: str, iters: int):
+    """One peak-rate probe (mcpd_probe): dict(per_cu_per_clock, per_second,
+    clock_hz, ms, cus)."""
+    r = ProbeResult()
+    _check(load().mcpd_probe(PROBES.index(kind), int(iters), C.byref(r)), "mcpd_probe")
+    return dict(per_cu_per_clock=r.per_cu_per_clock, per_second=r.per_second, clock_hz=r.clock_hz,
+                ms=r.ms, cus=int(r.cus))
 
 
 def mcpd_features(dec):

@@ -34,6 +34,16 @@ def test_struct_layouts_match_header():
     assert C.sizeof(N.RunOpts) == 8 + 18 * 4 + 4 * 8
     assert C.sizeof(N.RunStats) == 14 * 8 + 6 * 4 + 8
     assert C.sizeof(N.TuneEntry) == 32
+    assert C.sizeof(N.ProbeResult) == 4 * 8 + 2 * 4
+
+
+def test_probe_rejects_bad_arguments_before_any_device_call():
+    L = N.load()
+    r = N.ProbeResult()
+    assert L.mcpd_probe(-1, 10, C.byref(r)) == N.MCPD_EINVAL
+    assert L.mcpd_probe(len(N.PROBES), 10, C.byref(r)) == N.MCPD_EINVAL
+    assert L.mcpd_probe(0, 0, C.byref(r)) == N.MCPD_EINVAL
+    assert L.mcpd_probe(0, 10, None) == N.MCPD_EINVAL
 
 
 def test_run_opts_defaults():

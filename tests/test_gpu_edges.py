@@ -128,17 +128,19 @@ def test_strict_cap_reports_mcpd_ecap(kern):
 
 def test_numerator_workspace_limit_reports_mcpd_enomem():
     """The lane kernel's dense numerator rows (lanes x n x 8 bytes) are
-    capped at 64 GiB: 2^17 clones at two workgroups of 256 lanes per CU
-    would need 128 GiB, so the run returns MCPD_ENOMEM before allocating
-    anything, and the instance still runs at one workgroup per CU."""
+    capped at 64 GiB: 2^17 clones with enough slots (2^20) to fill two
+    workgroups of 256 lanes on every CU would need 128 GiB, so the run
+    returns MCPD_ENOMEM before allocating anything or launching, and the
+    instance still runs afterwards."""
     n = 1 << 17
     inst = I.make_instance(f"n{n}", n, 8000, 3, 8, 0.05, 0.1, prior=8 / n, seed=3)
     dec = N.Decoder(inst)
     try:
+        slots = 1 << 20
         with pytest.raises(N.McpdError) as e:
-            dec.run(256 * n, 256, n // 10 + 1, n, 10, kernel=1, wg_per_cu=2)
+            dec.run(slots * n, slots, n // 10 + 1, n, 10, kernel=1, wg_per_cu=2)
         assert e.value.code == N.MCPD_ENOMEM
-        ok = dec.run(256 * n, 256, n // 10 + 1, n, 10, kernel=1, wg_per_cu=1)
-        assert ok["stats"]["reps_retained"] == 256
+        ok = dec.run(256 * 2000, 256, 200, 2000, 10, kernel=1, wg_per_cu=1)
+        assert ok["stats"]["reps_retained"] >= 256
     finally:
         dec.close()
