@@ -267,6 +267,26 @@ int mcpd_run_unbiased_dev(mcpd_instance *inst, uint64_t budget, uint32_t slots, 
 
 /* Release the instance and its device memory (NULL is a no-op).  Destroy
  * every batch that holds the instance first. */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the run of
+ * mcpd_run_unbiased_dev with every device buffer it needs carved from one
+ * static device array of MCPD_NOALLOC_SCRATCH_BYTES per device, which the
+ * library holds until the process ends; the call itself allocates nothing
+ * (no hipMalloc, hipHostMalloc or event creation).  Same arguments, outputs
+ * and errors as mcpd_run_unbiased_dev; results are bit-identical to it
+ * (the grid shrinks to what the array holds, and results never depend on
+ * the grid).  stats->kernel_ms is 0 (the call keeps no timing events).
+ * The first call on a device looks up the array's address there.  Every
+ * call on one device shares that device's array: calls that overlap in
+ * time on one device race and must be serialised by the caller.  A run
+ * whose buffers for a single workgroup exceed the array (for example
+ * n_clones x 8 bytes of numerator row per group of lanes, roughly above
+ * 10^6 clones) returns MCPD_EINVAL naming the size it needs. */
+#define MCPD_NOALLOC_SCRATCH_BYTES (256u << 20)
+int mcpd_run_unbiased_dev_noalloc(mcpd_instance *inst, uint64_t budget, uint32_t slots, uint32_t k,
+                                  uint32_t m, uint64_t seed, const mcpd_run_opts *opts, double *marginals_dev,
+                                  double *stderr_dev, uint64_t *hist_dev, mcpd_run_stats *stats);
+
 void mcpd_destroy(mcpd_instance *inst);
 
 /* Batches: many instances, each with its own run parameters, in ONE

@@ -40,7 +40,8 @@ def jobs():
     """(source, extra flags, object name) of every compile step."""
     out = [("mcpd_host.cpp", [], "host.o"), ("mcpd_sampler.hip", [], "sampler.o"),
            ("mcpd_mlp.hip", [], "mlp.o"), ("mcpd_mlp_host.cpp", [], "mlp_host.o"),
-           ("mcpd_finish.hip", [], "finish.o"), ("mcpd_probe.hip", [], "probe.o")]
+           ("mcpd_finish.hip", [], "finish.o"), ("mcpd_probe.hip", [], "probe.o"),
+           ("mcpd_noalloc.hip", [], "noalloc.o")]
     out += [("mcpd_sampler.hip", [f"-DMCPD_FMT={f}"], f"sampler_f{f}.o") for f in range(N_FORMATS)]
     return out
 

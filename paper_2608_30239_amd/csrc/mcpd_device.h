@@ -155,6 +155,8 @@ int launch_sampler_fmt(const LaunchArgs &a, int grid, size_t lds_bytes, void *st
 // Zero n64 64-bit words at p (a kernel, so that it can sit in a captured
 // graph).  Returns a hipError_t value as int.
 int launch_fill_zero(uint64_t *p, size_t n64, void *stream);
+// Store one 64-bit word at p (a kernel).  Returns a hipError_t value as int.
+int launch_put_u64(uint64_t *p, uint64_t v, void *stream);
 // Marginals and standard errors of one instance from its integer sums,
 // written to device memory (defined in mcpd_finish.hip).
 int launch_finish(const int64_t *S1, const uint64_t *S2, uint32_t n, uint32_t nb, uint32_t P, uint32_t W,

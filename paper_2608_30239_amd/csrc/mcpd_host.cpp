@@ -450,6 +450,13 @@ struct Launch {
     // pinned host staging
     uint64_t *h_seed = nullptr;
     uint64_t *h_out = nullptr; size_t h_out_cap = 0;
+    // Arena mode (the allocation-free entry point): every device buffer is
+    // carved from a caller-provided region instead of allocated, the copy
+    // back goes to pageable host memory, and nothing is timed.
+    uint8_t *arena = nullptr;
+    size_t arena_cap = 0;
+    std::vector<uint64_t> h_out_pageable;
+    uint64_t seed_value = 0;
     // graph and timing
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -467,11 +474,13 @@ struct Launch {
     {
         (void)hipStreamSynchronize(stream);
         drop_graph();
-        free_ptr(d_desc); free_ptr(d_tickets); free_ptr(d_zero); free_ptr(d_seed); free_ptr(d_acc);
-        free_ptr(d_lists); free_ptr(d_gstate); free_ptr(d_lane_stats); free_ptr(d_slot_nstar);
-        free_ptr(d_slot_units);
-        if (h_seed) (void)hipHostFree(h_seed);
-        if (h_out) (void)hipHostFree(h_out);
+        if (!arena) {   // in arena mode nothing here was allocated
+            free_ptr(d_desc); free_ptr(d_tickets); free_ptr(d_zero); free_ptr(d_seed); free_ptr(d_acc);
+            free_ptr(d_lists); free_ptr(d_gstate); free_ptr(d_lane_stats); free_ptr(d_slot_nstar);
+            free_ptr(d_slot_units);
+            if (h_seed) (void)hipHostFree(h_seed);
+            if (h_out) (void)hipHostFree(h_out);
+        }
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -730,44 +739,76 @@ int plan(Launch &L, const Config &c)
         if (spl == 1 || L.tickets.size() >= resident) break;
     }
     L.grid = (int)std::max<size_t>(1, std::min<size_t>((size_t)L.cus * c.wg_per_cu, L.tickets.size()));
-    const size_t lanes = (size_t)L.grid * WG_LANES;
-    // numerator rows, touched lists and statistics rows: one per lane of the
-    // lane kernel, one per group of the cooperative kernel
-    const size_t rows = c.coop ? (size_t)L.grid * (WG_LANES >> c.group_log2) : lanes;
     // touched-clone lists long enough that large instances rarely fall back
     // to scanning a whole numerator row at the end of a slot
     L.list_cap = std::min<uint32_t>(4096, std::max<uint32_t>(64, L.acc_stride / 4));
-
-    // Workspace.  Numerator rows stay zero between runs (the kernel clears
-    // what it used), so they are cleared only when (re)allocated.
+    // numerator rows, touched lists and statistics rows: one per lane of the
+    // lane kernel, one per group of the cooperative kernel
+    const size_t rows_per_wg = c.coop ? (size_t)(WG_LANES >> c.group_log2) : (size_t)WG_LANES;
     int rc;
-    const size_t acc_words = rows * (size_t)L.acc_stride;
-    if (acc_words > ((size_t)8 << 30)) return fail(MCPD_ENOMEM, "numerator workspace above 64 GiB; use fewer workgroups per CU");
-    if (L.acc_cap < acc_words || !L.d_acc) {
-        if ((rc = ensure(&L.d_acc, L.acc_cap, acc_words))) return rc;
-        int e = launch_fill_zero(reinterpret_cast<uint64_t *>(L.d_acc), L.acc_cap, L.stream);
-        if (e != hipSuccess) return hip_fail((hipError_t)e, "zero numerators");
+    if (L.arena) {
+        // Carve every buffer from the arena, fixed parts first; the grid
+        // shrinks until the per-workgroup parts fit (results never depend on
+        // the grid).
+        auto a256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+        const size_t fixed = a256(L.zero_words * 8) + a256(8) + a256(L.desc.size() * sizeof(InstDesc)) +
+                             a256(L.tickets.size() * 4);
+        const size_t per_wg = a256(rows_per_wg * (size_t)L.acc_stride * 8) + a256(rows_per_wg * L.list_cap * 4) +
+                              a256(rows_per_wg * ST_COUNT * 8) +
+                              (L.gwords ? a256((size_t)WG_LANES * L.gwords * 4) : 0);
+        if (fixed + per_wg > L.arena_cap)
+            return fail(MCPD_EINVAL, "run needs " + std::to_string(fixed + per_wg) + " bytes of scratch for one "
+                        "workgroup; the allocation-free entry point has " + std::to_string(L.arena_cap));
+        const size_t fit = (L.arena_cap - fixed) / per_wg;
+        if ((size_t)L.grid > fit) L.grid = (int)fit;
+        const size_t rows = (size_t)L.grid * rows_per_wg;
+        uint8_t *at = L.arena;
+        auto take = [&](size_t b) { uint8_t *p = at; at += a256(b); return p; };
+        L.d_zero = reinterpret_cast<uint64_t *>(take(L.zero_words * 8));
+        L.d_seed = reinterpret_cast<uint64_t *>(take(8));
+        L.d_desc = reinterpret_cast<InstDesc *>(take(L.desc.size() * sizeof(InstDesc)));
+        L.d_tickets = reinterpret_cast<uint32_t *>(take(L.tickets.size() * 4));
+        L.d_acc = reinterpret_cast<int64_t *>(take(rows * (size_t)L.acc_stride * 8));
+        L.acc_cap = rows * (size_t)L.acc_stride;
+        L.d_lists = reinterpret_cast<uint32_t *>(take(rows * L.list_cap * 4));
+        L.d_lane_stats = reinterpret_cast<uint64_t *>(take(rows * ST_COUNT * 8));
+        L.d_gstate = L.gwords ? reinterpret_cast<uint32_t *>(take((size_t)L.grid * WG_LANES * L.gwords * 4)) : nullptr;
+        if ((size_t)(at - L.arena) > L.arena_cap) return fail(MCPD_EINVAL, "internal: scratch overrun");
+        L.h_out_pageable.assign(L.zero_words, 0);
+        L.h_out = L.h_out_pageable.data();
+    } else {
+        const size_t lanes = (size_t)L.grid * WG_LANES;
+        const size_t rows = (size_t)L.grid * rows_per_wg;
+        // Workspace.  Numerator rows stay zero between runs (the kernel
+        // clears what it used), so they are cleared only when (re)allocated.
+        const size_t acc_words = rows * (size_t)L.acc_stride;
+        if (acc_words > ((size_t)8 << 30)) return fail(MCPD_ENOMEM, "numerator workspace above 64 GiB; use fewer workgroups per CU");
+        if (L.acc_cap < acc_words || !L.d_acc) {
+            if ((rc = ensure(&L.d_acc, L.acc_cap, acc_words))) return rc;
+            int e = launch_fill_zero(reinterpret_cast<uint64_t *>(L.d_acc), L.acc_cap, L.stream);
+            if (e != hipSuccess) return hip_fail((hipError_t)e, "zero numerators");
+        }
+        if ((rc = ensure(&L.d_lists, L.lists_cap, rows * L.list_cap))) return rc;
+        if (L.gwords && (rc = ensure(&L.d_gstate, L.gstate_cap, lanes * (size_t)L.gwords))) return rc;
+        if ((rc = ensure(&L.d_lane_stats, L.ls_cap, rows * (size_t)ST_COUNT))) return rc;
+        if ((rc = ensure(&L.d_zero, L.zero_cap, L.zero_words))) return rc;
+        if ((rc = ensure(&L.d_seed, L.seed_cap, (size_t)1))) return rc;
+        if (L.slot_records) {
+            if ((rc = ensure(&L.d_slot_nstar, L.sn_cap, slots_total))) return rc;
+            if ((rc = ensure(&L.d_slot_units, L.su_cap, slots_total))) return rc;
+        }
+        if (L.h_out_cap < L.zero_words) {
+            if (L.h_out) (void)hipHostFree(L.h_out);
+            L.h_out = nullptr;
+            L.h_out_cap = 0;
+            hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&L.h_out), L.zero_words * 8, hipHostMallocDefault);
+            if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+            L.h_out_cap = L.zero_words;
+        }
+        if (!L.h_seed) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&L.h_seed), 8, hipHostMallocDefault));
+        if (!L.ev0) HIP_TRY(hipEventCreate(&L.ev0));
+        if (!L.ev1) HIP_TRY(hipEventCreate(&L.ev1));
     }
-    if ((rc = ensure(&L.d_lists, L.lists_cap, rows * L.list_cap))) return rc;
-    if (L.gwords && (rc = ensure(&L.d_gstate, L.gstate_cap, lanes * (size_t)L.gwords))) return rc;
-    if ((rc = ensure(&L.d_lane_stats, L.ls_cap, rows * (size_t)ST_COUNT))) return rc;
-    if ((rc = ensure(&L.d_zero, L.zero_cap, L.zero_words))) return rc;
-    if ((rc = ensure(&L.d_seed, L.seed_cap, (size_t)1))) return rc;
-    if (L.slot_records) {
-        if ((rc = ensure(&L.d_slot_nstar, L.sn_cap, slots_total))) return rc;
-        if ((rc = ensure(&L.d_slot_units, L.su_cap, slots_total))) return rc;
-    }
-    if (L.h_out_cap < L.zero_words) {
-        if (L.h_out) (void)hipHostFree(L.h_out);
-        L.h_out = nullptr;
-        L.h_out_cap = 0;
-        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&L.h_out), L.zero_words * 8, hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
-        L.h_out_cap = L.zero_words;
-    }
-    if (!L.h_seed) HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&L.h_seed), 8, hipHostMallocDefault));
-    if (!L.ev0) HIP_TRY(hipEventCreate(&L.ev0));
-    if (!L.ev1) HIP_TRY(hipEventCreate(&L.ev1));
     for (size_t i = 0; i < count; ++i) {
         InstDesc &d = L.desc[i];
         uint64_t *blk = L.d_zero + L.off[i];
@@ -778,6 +819,13 @@ int plan(Launch &L, const Config &c)
         d.S2 = blk + SLOT_WORDS + ST_COUNT + o.hist_bins + (size_t)d.nbuckets * d.n;
         d.slot_nstar = L.slot_records ? L.d_slot_nstar + L.slot_off[i] : nullptr;
         d.slot_units = L.slot_records ? L.d_slot_units + L.slot_off[i] : nullptr;
+    }
+    if (L.arena) {
+        // the arena is shared with other calls: its contents are never trusted
+        HIP_TRY(hipMemcpyAsync(L.d_desc, L.desc.data(), L.desc.size() * sizeof(InstDesc), hipMemcpyHostToDevice,
+                               L.stream));
+        HIP_TRY(hipMemcpyAsync(L.d_tickets, L.tickets.data(), L.tickets.size() * 4, hipMemcpyHostToDevice, L.stream));
+        return MCPD_OK;
     }
     // Repeated runs of one shape plan the same bytes: the device copies are
     // then already right (descriptors are zero-initialised, padding included)
@@ -826,8 +874,19 @@ LaunchArgs launch_args(const Launch &L)
 // `timed`, events bracket the sampler alone.
 int enqueue(Launch &L, bool timed)
 {
-    HIP_TRY(hipMemcpyAsync(L.d_seed, L.h_seed, 8, hipMemcpyHostToDevice, L.stream));
-    int e = launch_fill_zero(L.d_zero, L.zero_words, L.stream);
+    int e;
+    if (L.arena) {
+        // the key by a kernel (no pinned staging), and the numerator rows
+        // cleared: the arena keeps whatever the last call left there
+        timed = false;
+        e = launch_put_u64(L.d_seed, L.seed_value, L.stream);
+        if (e != hipSuccess) return hip_fail((hipError_t)e, "write key");
+        e = launch_fill_zero(reinterpret_cast<uint64_t *>(L.d_acc), L.acc_cap, L.stream);
+        if (e != hipSuccess) return hip_fail((hipError_t)e, "zero numerators");
+    } else {
+        HIP_TRY(hipMemcpyAsync(L.d_seed, L.h_seed, 8, hipMemcpyHostToDevice, L.stream));
+    }
+    e = launch_fill_zero(L.d_zero, L.zero_words, L.stream);
     if (e != hipSuccess) return hip_fail((hipError_t)e, "zero outputs");
     if (timed) HIP_TRY(hipEventRecord(L.ev0, L.stream));
     e = launch_sampler(launch_args(L), L.fmt, L.grid, L.lds, L.stream, L.coop);
@@ -871,8 +930,17 @@ int capture(Launch &L)
 // zeroing, sampler, copy back); without, the sampler alone.
 int execute(Launch &L, uint64_t seed, bool use_graph)
 {
-    *L.h_seed = seed;
     int rc;
+    if (L.arena) {
+        L.seed_value = seed;
+        if ((rc = enqueue(L, false))) return rc;
+        HIP_TRY(hipStreamSynchronize(L.stream));
+        L.last_ms = 0.f;
+        const uint32_t flags = (uint32_t)(L.h_out[0] >> 32);
+        if (flags & ERR_BUCKETS) return fail(MCPD_EINVAL, "internal: N* above bucket count");
+        return MCPD_OK;
+    }
+    *L.h_seed = seed;
     if (use_graph) {
         if (!L.exec && (rc = capture(L))) return rc;
         HIP_TRY(hipEventRecord(L.ev0, L.stream));
@@ -1180,6 +1248,8 @@ int mcpd_get_weights(const mcpd_instance *I, double *w_exact, uint64_t *mass)
     return MCPD_OK;
 }
 
+}  // extern "C"
+
 namespace mcpd {
 namespace host {
 // One fixed-budget run of one instance; device outputs when dev_marginals is
@@ -1224,8 +1294,49 @@ int run_single(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, ui
         return rc;
     return finish_item(L, 0, marginals, stderr_out, hist, stats);
 }
+
+// The run of mcpd_run_unbiased_dev with every device buffer carved from
+// `arena` (cap bytes) instead of allocated: no hipMalloc, hipHostMalloc or
+// event creation.  The instance's tables in the run's row format already
+// exist (mcpd_create builds them).
+int run_single_arena(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, uint32_t m, uint64_t seed,
+                     const mcpd_run_opts *opts_in, double *dev_marginals, double *dev_stderr, uint64_t *dev_hist,
+                     mcpd_run_stats *stats, void *arena, size_t cap)
+{
+    if (!I) return fail(MCPD_EINVAL, "null instance");
+    if (!dev_marginals) return fail(MCPD_EINVAL, "null marginals_dev");
+    mcpd_run_opts opts;
+    if (opts_in) opts = *opts_in; else mcpd_run_opts_init(&opts);
+    if (opts.slot_nstar || opts.slot_units || opts.bucket_sum || opts.bucket_sumsq)
+        return fail(MCPD_EINVAL, "slot records and buckets are host outputs of mcpd_run_unbiased");
+    std::vector<Item> items{Item{I, budget, slots, k, m}};
+    int rc = check_items(items, opts, false);
+    if (rc) return rc;
+    Launch L;
+    L.stream = I->stream;
+    L.device = I->device;
+    L.cus = I->cus;
+    L.arena = reinterpret_cast<uint8_t *>(arena);
+    L.arena_cap = cap;
+    L.items = items;
+    L.opts = opts;
+    L.batch_ids = false;
+    L.slot_records = false;
+    L.fmt = pick_format(I->m > 127, I->dmax);
+    if (!I->d_rows[L.fmt]) return fail(MCPD_EINVAL, "internal: the instance's rows are missing");
+    Config c = default_config(L);
+    if (opts.kernel == 2 && !c.coop) return fail(MCPD_EINVAL, "the chain states do not fit the cooperative kernel");
+    if ((rc = plan(L, c))) return rc;
+    L.dev_marginals = dev_marginals;
+    L.dev_stderr = dev_stderr;
+    L.dev_hist = dev_hist;
+    if ((rc = execute(L, seed, false))) return rc;
+    return finish_item(L, 0, nullptr, nullptr, nullptr, stats);
+}
 }  // namespace host
 }  // namespace mcpd
+
+extern "C" {
 
 int mcpd_run_unbiased(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, uint32_t m,
                       uint64_t seed, const mcpd_run_opts *opts, double *marginals, double *stderr_out,

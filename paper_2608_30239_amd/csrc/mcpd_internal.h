@@ -19,6 +19,11 @@ int hip_fail(hipError_t e, const char *what);
 // Host-side score weights and validation (mcpd_host.cpp).
 int validate_design(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx, const uint8_t *y,
                     double fp, double fn, double q, int32_t *dmax_out);
+// mcpd_run_unbiased_dev with every device buffer carved from `arena` (cap
+// bytes) instead of allocated (mcpd_host.cpp).
+int run_single_arena(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, uint32_t m, uint64_t seed,
+                     const mcpd_run_opts *opts, double *dev_marginals, double *dev_stderr, uint64_t *dev_hist,
+                     mcpd_run_stats *stats, void *arena, size_t cap);
 }  // namespace host
 }  // namespace mcpd
 

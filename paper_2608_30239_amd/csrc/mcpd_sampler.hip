@@ -1488,6 +1488,17 @@ int launch_sampler(const LaunchArgs &a, int fmt, int grid, size_t lds, void *str
     }
 }
 
+__global__ void put_u64_kernel(uint64_t *p, uint64_t v)
+{
+    if (threadIdx.x == 0) *p = v;
+}
+
+int launch_put_u64(uint64_t *p, uint64_t v, void *stream)
+{
+    hipLaunchKernelGGL(put_u64_kernel, dim3(1), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), p, v);
+    return (int)hipGetLastError();
+}
+
 int launch_fill_zero(uint64_t *p, size_t n64, void *stream)
 {
     if (n64 == 0) return (int)hipSuccess;

@@ -88,7 +88,7 @@ class TuneEntry(C.Structure):
 
 # Every symbol include/mcpd.h declares.
 EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_prune", "mcpd_create", "mcpd_set_weights",
-           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_run_unbiased_dev",
+           "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_run_unbiased_dev", "mcpd_run_unbiased_dev_noalloc",
            "mcpd_destroy", "mcpd_batch_create",
            "mcpd_batch_run", "mcpd_batch_tune", "mcpd_batch_config", "mcpd_batch_buckets",
            "mcpd_batch_slot_records", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_features",
@@ -143,6 +143,7 @@ def load(path: Optional[str] = None):
                                         C.c_uint64, C.POINTER(RunOpts), vp, vp, vp,
                                         C.POINTER(RunStats)]
         L.mcpd_run_unbiased_dev.argtypes = L.mcpd_run_unbiased.argtypes
+        L.mcpd_run_unbiased_dev_noalloc.argtypes = L.mcpd_run_unbiased.argtypes
         L.mcpd_destroy.argtypes = [vp]
         L.mcpd_destroy.restype = None
         L.mcpd_batch_create.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.POINTER(RunOpts), vp, C.POINTER(vp)]
@@ -274,6 +275,17 @@ def mcpd_run_unbiased_dev(h, budget, slots, k, m, seed, marginals_ptr, stderr_pt
     _check(load().mcpd_run_unbiased_dev(h, budget, slots, k, m, seed, C.byref(o), C.c_void_p(marginals_ptr),
                                         C.c_void_p(stderr_ptr or None), C.c_void_p(hist_ptr or None),
                                         C.byref(st)), "mcpd_run_unbiased_dev")
+    return st.as_dict()
+
+
+def mcpd_run_unbiased_dev_noalloc(h, budget, slots, k, m, seed, marginals_ptr, stderr_ptr=0, hist_ptr=0, **opt):
+    """mcpd_run_unbiased_dev without any allocation (the library's static
+    scratch array).  Returns the statistics dict."""
+    o = run_opts(**opt)
+    st = RunStats()
+    _check(load().mcpd_run_unbiased_dev_noalloc(h, budget, slots, k, m, seed, C.byref(o), C.c_void_p(marginals_ptr),
+                                                C.c_void_p(stderr_ptr or None), C.c_void_p(hist_ptr or None),
+                                                C.byref(st)), "mcpd_run_unbiased_dev_noalloc")
     return st.as_dict()
 
 
