@@ -120,6 +120,13 @@ typedef struct mcpd_run_opts {
                                N*_p = row+1 (V = W * slot numerator, exact)     */
     uint64_t *bucket_sumsq; /* [bucket_rows * n * 2] (low, high) words of the
                                128-bit sum of V_pj^2, same grouping            */
+    uint64_t *mismatch;     /* host, [n] or NULL (mcpd_run_unbiased only): the
+                               mismatch time of every clone, summed over the
+                               retained replications of every slot: the number
+                               of time indices s = 1..C at which
+                               x_j(s) != y_j(s-1), i.e. how long the pair spent
+                               apart at clone j before it met (Algorithm 3);
+                               for batches see mcpd_batch_mismatch             */
 } mcpd_run_opts;
 
 /* Run statistics of one instance (all integers exact). */
@@ -344,6 +351,10 @@ int mcpd_batch_buckets(const mcpd_batch *batch, int32_t index, uint32_t rows, in
 /* N*_p and S_p of every slot of instance `index` from the last run (host
  * [slots]; either may be NULL).  Needs opts.keep_slot_records at creation. */
 int mcpd_batch_slot_records(mcpd_batch *batch, int32_t index, uint32_t *nstar, uint64_t *units);
+
+/* Mismatch times of instance `index` of the last batch run (host, n values;
+ * as mcpd_run_opts.mismatch).  Errors: MCPD_EINVAL (null, index out of range). */
+int mcpd_batch_mismatch(const mcpd_batch *batch, int32_t index, uint64_t *out);
 
 /* Release a batch (NULL is a no-op); the instances stay. */
 void mcpd_batch_destroy(mcpd_batch *batch);

@@ -26,6 +26,8 @@
  *                            cost C = max(l, tau); identity-design tau law
  *   slot scheduler ......... per-slot refill/retention rules from the records
  *   aggregate .............. mean over slots vs exact posterior marginals (CI)
+ *   mismatch time .......... literal count of x_j(s) != y_j(s-1) on the trace;
+ *                            run totals = sums over retained replications
  * Trajectory bits themselves have no printed worked example in the paper:
  * beyond the pins above they are parity unpinned.
  */
@@ -547,6 +549,7 @@ typedef struct {
     int32_t *mwhere;
     int32_t nmis;
     acc_t rep;         /* numerators of the current replication */
+    acc_t rmis;        /* its mismatch time per clone: #{s >= 1 : x_j(s) != y_j(s-1)} */
     acc_t slot;        /* numerators summed over retained replications */
 } scratch_t;
 
@@ -559,7 +562,7 @@ static int scratch_alloc(scratch_t *s, int32_t n, int32_t m)
     if (!s->mis || !s->mwhere) rc = MO_ENOMEM;
     else for (int32_t i = 0; i < n; ++i) s->mwhere[i] = -1;
     s->nmis = 0;
-    rc |= acc_alloc(&s->rep, n) | acc_alloc(&s->slot, n);
+    rc |= acc_alloc(&s->rep, n) | acc_alloc(&s->slot, n) | acc_alloc(&s->rmis, n);
     return rc ? MO_ENOMEM : MO_OK;
 }
 
@@ -567,7 +570,7 @@ static void scratch_free(scratch_t *s)
 {
     chain_free(&s->X); chain_free(&s->Y);
     free(s->mis); free(s->mwhere);
-    acc_free(&s->rep); acc_free(&s->slot);
+    acc_free(&s->rep); acc_free(&s->slot); acc_free(&s->rmis);
 }
 
 static void mis_update(scratch_t *s, int32_t i)
@@ -613,6 +616,11 @@ typedef struct {
  * a cap keeps the terms up to its last time index (the truncated H^{(R)}). */
 static void add_time_index(scratch_t *s, uint64_t tidx, uint64_t k, uint64_t ell, uint64_t W)
 {
+    /* mismatch time: every time index s >= 1 at which x_j(s) != y_j(s-1)
+     * counts once for clone j (the per-clone share of the time the pair
+     * spends apart before it meets, Algorithm 3; zero after the meeting) */
+    if (tidx >= 1)
+        for (int32_t e = 0; e < s->nmis; ++e) acc_add(&s->rmis, s->mis[e], 1);
     if (tidx >= k && tidx <= ell)
         for (int32_t e = 0; e < s->X.npos; ++e) acc_add(&s->rep, s->X.pos[e], 1);
     if (tidx >= k + 1 && s->nmis > 0) {
@@ -671,6 +679,7 @@ static int run_replication(const mo_model *M, const mo_params *P, uint32_t p, ui
     chain_reset(M, &s->Y);
     while (s->nmis > 0) { s->mwhere[s->mis[s->nmis - 1]] = -1; s->nmis--; }
     acc_clear(&s->rep);
+    acc_clear(&s->rmis);
     if (P->init_mode == 1) draw_prior_state(M, P, p, r, s);
 
     /* time index 0 */
@@ -715,7 +724,7 @@ static int run_replication(const mo_model *M, const mo_params *P, uint32_t p, ui
 
 /* Trace of one replication (tests; small n). */
 int mo_trace(const mo_model *M, const mo_params *P, uint32_t p, uint32_t r, uint64_t max_len,
-             uint8_t *X, uint8_t *Y, int32_t *I, uint64_t *U, int64_t *numer, uint64_t out[3])
+             uint8_t *X, uint8_t *Y, int32_t *I, uint64_t *U, int64_t *numer, int64_t *mismatch, uint64_t out[3])
 {
     if (P->k > P->ell || P->u_hi_bits < 1 || P->u_hi_bits > 32 || P->init_mode > 1) return MO_EINVAL;
     scratch_t s;
@@ -725,6 +734,7 @@ int mo_trace(const mo_model *M, const mo_params *P, uint32_t p, uint32_t r, uint
     int rc = run_replication(M, P, p, r, &s, &ro, &tr);
     if (!rc) {
         for (int32_t j = 0; j < M->n; ++j) numer[j] = s.rep.v[j];
+        if (mismatch) for (int32_t j = 0; j < M->n; ++j) mismatch[j] = s.rmis.v[j];
         out[0] = ro.C; out[1] = ro.tau; out[2] = (uint64_t)ro.capped;
         if (tr.overflow) rc = MO_ETOOLONG;
     }
@@ -761,7 +771,7 @@ enum {
 };
 
 static int run_slot(const mo_model *M, const mo_params *P, uint64_t B, uint32_t p,
-                    scratch_t *s, slot_rec_t *rec, stats_t *st, uint64_t *hist)
+                    scratch_t *s, slot_rec_t *rec, stats_t *st, uint64_t *hist, uint64_t *mis_tot)
 {
     acc_clear(&s->slot);
     uint64_t S = 0;
@@ -782,6 +792,9 @@ static int run_slot(const mo_model *M, const mo_params *P, uint64_t B, uint32_t 
         }
         nret += 1;
         acc_merge(&s->slot, &s->rep);
+        if (mis_tot)
+            for (int32_t e = 0; e < s->rmis.nlist; ++e)
+                mis_tot[s->rmis.list[e]] += (uint64_t)s->rmis.v[s->rmis.list[e]];
         st->retained_units += ro.C;
         st->reps_retained += 1;
         if (ro.capped) {
@@ -821,11 +834,13 @@ static int run_slot(const mo_model *M, const mo_params *P, uint64_t B, uint32_t 
  *   stderr_j = sqrt( sum_p (A_pj - marginal_j)^2 / (P-1) / P )  (reading:
  *   slots are i.i.d. by Assumption 2; NaN when P = 1).
  * Optional outputs: per-slot N*, S_p(N*), discarded C; integer buckets
- * bucket[n-1][j] = sum_{p: N*_p = n} V_pj and the 128-bit sums of V_pj^2. */
+ * bucket[n-1][j] = sum_{p: N*_p = n} V_pj and the 128-bit sums of V_pj^2;
+ * mismatch[j] = the mismatch time of clone j summed over every retained
+ * replication of every slot. */
 int mo_run(const mo_model *M, const mo_params *P, double *marginals, double *stderr_out,
            uint64_t *hist, uint64_t *stats_out, uint32_t *slot_nstar, uint64_t *slot_sret,
            uint64_t *slot_disc, int64_t *bucket1, uint64_t *bucket2, uint64_t nbuckets,
-           int32_t nthreads)
+           uint64_t *mismatch, int32_t nthreads)
 {
     if (P->slots == 0 || P->slots > 0xFFFFFFFFull) return MO_EINVAL;
     if (P->k > P->ell || P->ell > (1ull << 31)) return MO_EINVAL;
@@ -841,7 +856,8 @@ int mo_run(const mo_model *M, const mo_params *P, double *marginals, double *std
     stats_t total;
     memset(&total, 0, sizeof(total));
     uint64_t *hist_total = (uint64_t *)calloc((size_t)P->hist_bins, sizeof(uint64_t));
-    if (!hist_total) { free(recs); return MO_ENOMEM; }
+    uint64_t *mis_total = (uint64_t *)calloc((size_t)n, sizeof(uint64_t));
+    if (!hist_total || !mis_total) { free(recs); free(hist_total); free(mis_total); return MO_ENOMEM; }
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -851,12 +867,13 @@ int mo_run(const mo_model *M, const mo_params *P, double *marginals, double *std
         stats_t st;
         memset(&st, 0, sizeof(st));
         uint64_t *h = (uint64_t *)calloc((size_t)P->hist_bins, sizeof(uint64_t));
+        uint64_t *dm = mismatch ? (uint64_t *)calloc((size_t)n, sizeof(uint64_t)) : NULL;
         int lrc = scratch_alloc(&s, n, M->m);
-        if (!h) lrc = MO_ENOMEM;
+        if (!h || (mismatch && !dm)) lrc = MO_ENOMEM;
 #pragma omp for schedule(dynamic, 8)
         for (int64_t p = 0; p < (int64_t)Pn; ++p) {
             if (lrc) continue;
-            lrc = run_slot(M, P, B, (uint32_t)p, &s, &recs[p], &st, h);
+            lrc = run_slot(M, P, B, (uint32_t)p, &s, &recs[p], &st, h, dm);
         }
 #pragma omp critical
         {
@@ -872,8 +889,10 @@ int mo_run(const mo_model *M, const mo_params *P, double *marginals, double *std
             total.discarded_units += st.discarded_units;
             if (st.nstar_max > total.nstar_max) total.nstar_max = st.nstar_max;
             if (h) for (uint64_t b = 0; b < P->hist_bins; ++b) hist_total[b] += h[b];
+            if (dm) for (int32_t j = 0; j < n; ++j) mis_total[j] += dm[j];
         }
         free(h);
+        free(dm);
         scratch_free(&s);
     }
     if (rc) goto done;
@@ -925,6 +944,7 @@ int mo_run(const mo_model *M, const mo_params *P, double *marginals, double *std
         }
     }
     for (uint64_t b = 0; b < P->hist_bins; ++b) hist[b] = hist_total[b];
+    if (mismatch) memcpy(mismatch, mis_total, (size_t)n * sizeof(uint64_t));
     stats_out[ST_RETAINED_UNITS] = total.retained_units;
     stats_out[ST_SINGLE_SITE] = total.single_site;
     stats_out[ST_REPS_RETAINED] = total.reps_retained;
@@ -944,6 +964,7 @@ done:
     for (uint64_t p = 0; p < Pn; ++p) { free(recs[p].ent_j); free(recs[p].ent_v); }
     free(recs);
     free(hist_total);
+    free(mis_total);
     return rc;
 }
 
@@ -959,7 +980,7 @@ int mo_slot(const mo_model *M, const mo_params *P, uint32_t p, int64_t *numer, u
     uint64_t *h = (uint64_t *)calloc((size_t)P->hist_bins, sizeof(uint64_t));
     slot_rec_t rec;
     memset(&rec, 0, sizeof(rec));
-    int rc = h ? run_slot(M, P, P->budget / P->slots, p, &s, &rec, &st, h) : MO_ENOMEM;
+    int rc = h ? run_slot(M, P, P->budget / P->slots, p, &s, &rec, &st, h, NULL) : MO_ENOMEM;
     if (!rc) {
         memset(numer, 0, (size_t)M->n * sizeof(int64_t));
         for (int32_t e = 0; e < rec.nent; ++e) numer[rec.ent_j[e]] = rec.ent_v[e];

@@ -75,9 +75,9 @@ def lib():
             L.mo_gibbs_step.argtypes = [vp, vp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                         C.c_uint64, C.c_uint32, vp, vp]
             L.mo_trace.argtypes = [vp, C.POINTER(Params), C.c_uint32, C.c_uint32, C.c_uint64,
-                                   vp, vp, vp, vp, vp, vp]
+                                   vp, vp, vp, vp, vp, vp, vp]
             L.mo_run.argtypes = [vp, C.POINTER(Params), vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                 C.c_uint64, C.c_int32]
+                                 C.c_uint64, vp, C.c_int32]
             L.mo_slot.argtypes = [vp, C.POINTER(Params), C.c_uint32, vp, vp]
             _lib = L
     return _lib
@@ -221,13 +221,14 @@ class Model:
         I = np.zeros(max_len, np.int32)
         U = np.zeros(max_len, np.uint64)
         numer = np.zeros(n, np.int64)
+        mis = np.zeros(n, np.int64)
         out = np.zeros(3, np.uint64)
         rc = lib().mo_trace(self.h, C.byref(P), p, r, max_len, _ptr(X), _ptr(Y), _ptr(I), _ptr(U),
-                            _ptr(numer), _ptr(out))
+                            _ptr(numer), _ptr(mis), _ptr(out))
         if rc:
             raise ValueError(f"mo_trace failed ({rc})")
         Cn, tau, capped = (int(v) for v in out)
-        return dict(X=X[:Cn + 1], Y=Y[:Cn], I=I[:Cn], U=U[:Cn], numer=numer, C=Cn, tau=tau,
+        return dict(X=X[:Cn + 1], Y=Y[:Cn], I=I[:Cn], U=U[:Cn], numer=numer, mismatch=mis, C=Cn, tau=tau,
                     capped=bool(capped))
 
     def run(self, budget, slots, k, m, seed=0, nthreads=0, slot_records=False, buckets=None,
@@ -247,11 +248,12 @@ class Model:
         if buckets:
             b1 = np.zeros((buckets, n), np.int64)
             b2 = np.zeros((buckets, n, 2), np.uint64)
+        mis = np.zeros(n, np.uint64)
         rc = lib().mo_run(self.h, C.byref(P), _ptr(marg), _ptr(se), _ptr(hist), _ptr(stats),
-                          _ptr(ns), _ptr(sr), _ptr(sd), _ptr(b1), _ptr(b2), buckets or 0, nthreads)
+                          _ptr(ns), _ptr(sr), _ptr(sd), _ptr(b1), _ptr(b2), buckets or 0, _ptr(mis), nthreads)
         if rc:
             raise ValueError(f"mo_run failed ({rc})")
-        res = dict(marginals=marg, stderr=se, hist=hist,
+        res = dict(marginals=marg, stderr=se, hist=hist, mismatch=mis,
                    stats={k_: int(v) for k_, v in zip(STAT_NAMES, stats)})
         if slot_records:
             res.update(slot_nstar=ns, slot_sret=sr, slot_disc=sd)

@@ -100,6 +100,7 @@ struct InstDesc {
     // Outputs (zeroed before the launch).
     int64_t *S1;            // [nbuckets * n]
     uint64_t *S2;           // [nbuckets * n * 3]: limbs of the 128-bit sums of squares
+    int64_t *Dmis;          // [n]: mismatch time per clone, summed over retained replications
     uint64_t *hist;         // [hist_bins]
     uint64_t *stats;        // [ST_COUNT]
     uint32_t *next_slot;    // [XCDS * SLOT_CTR_STRIDE]: slot counters, one per XCD

@@ -400,10 +400,10 @@ bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t bud
 }
 
 // Words of one instance's block of outputs: slot counters, statistics,
-// histogram, S1, S2.
+// histogram, S1, S2, mismatch times.
 size_t block_words(size_t n, size_t nb, uint32_t hist_bins)
 {
-    return SLOT_WORDS + ST_COUNT + hist_bins + nb * n + 3 * nb * n;
+    return SLOT_WORDS + ST_COUNT + hist_bins + nb * n + 3 * nb * n + n;
 }
 
 struct Launch {
@@ -817,6 +817,7 @@ int plan(Launch &L, const Config &c)
         d.hist = blk + SLOT_WORDS + ST_COUNT;
         d.S1 = reinterpret_cast<int64_t *>(blk + SLOT_WORDS + ST_COUNT + o.hist_bins);
         d.S2 = blk + SLOT_WORDS + ST_COUNT + o.hist_bins + (size_t)d.nbuckets * d.n;
+        d.Dmis = reinterpret_cast<int64_t *>(d.S2 + 3 * (size_t)d.nbuckets * d.n);
         d.slot_nstar = L.slot_records ? L.d_slot_nstar + L.slot_off[i] : nullptr;
         d.slot_units = L.slot_records ? L.d_slot_units + L.slot_off[i] : nullptr;
     }
@@ -1049,6 +1050,16 @@ int copy_buckets(const Launch &L, size_t i, uint32_t rows, int64_t *sum, uint64_
             sumsq[2 * idx + 1] = (uint64_t)(v >> 64);
         }
     }
+    return MCPD_OK;
+}
+
+// Mismatch times of item i (n values).
+int copy_mismatch(const Launch &L, size_t i, uint64_t *out)
+{
+    const InstDesc &d = L.desc[i];
+    const size_t n = (size_t)d.n, nb = L.nb[i];
+    const uint64_t *blk = L.h_out + L.off[i];
+    std::memcpy(out, blk + SLOT_WORDS + ST_COUNT + L.opts.hist_bins + 4 * nb * n, n * sizeof(uint64_t));
     return MCPD_OK;
 }
 
@@ -1292,6 +1303,7 @@ int run_single(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t k, ui
     if ((opts.bucket_sum || opts.bucket_sumsq) &&
         (rc = copy_buckets(L, 0, opts.bucket_rows, opts.bucket_sum, opts.bucket_sumsq)))
         return rc;
+    if (opts.mismatch && (rc = copy_mismatch(L, 0, opts.mismatch))) return rc;
     return finish_item(L, 0, marginals, stderr_out, hist, stats);
 }
 
@@ -1307,8 +1319,8 @@ int run_single_arena(mcpd_instance *I, uint64_t budget, uint32_t slots, uint32_t
     if (!dev_marginals) return fail(MCPD_EINVAL, "null marginals_dev");
     mcpd_run_opts opts;
     if (opts_in) opts = *opts_in; else mcpd_run_opts_init(&opts);
-    if (opts.slot_nstar || opts.slot_units || opts.bucket_sum || opts.bucket_sumsq)
-        return fail(MCPD_EINVAL, "slot records and buckets are host outputs of mcpd_run_unbiased");
+    if (opts.slot_nstar || opts.slot_units || opts.bucket_sum || opts.bucket_sumsq || opts.mismatch)
+        return fail(MCPD_EINVAL, "slot records, buckets and mismatch times are host outputs of mcpd_run_unbiased");
     std::vector<Item> items{Item{I, budget, slots, k, m}};
     int rc = check_items(items, opts, false);
     if (rc) return rc;
@@ -1354,8 +1366,8 @@ int mcpd_run_unbiased_dev(mcpd_instance *I, uint64_t budget, uint32_t slots, uin
 {
     using namespace mcpd::host;
     if (!marginals_dev) return fail(MCPD_EINVAL, "null marginals_dev");
-    if (opts && (opts->slot_nstar || opts->slot_units || opts->bucket_sum || opts->bucket_sumsq))
-        return fail(MCPD_EINVAL, "slot records and buckets are host outputs of mcpd_run_unbiased");
+    if (opts && (opts->slot_nstar || opts->slot_units || opts->bucket_sum || opts->bucket_sumsq || opts->mismatch))
+        return fail(MCPD_EINVAL, "slot records, buckets and mismatch times are host outputs of mcpd_run_unbiased");
     return run_single(I, budget, slots, k, m, seed, opts, nullptr, nullptr, nullptr, stats, marginals_dev,
                       stderr_dev, hist_dev);
 }
@@ -1378,7 +1390,7 @@ int mcpd_batch_create(mcpd_instance *const *insts, int32_t count, const uint64_t
     if (count <= 0 || !insts || !budget || !slots || !k || !m) return fail(MCPD_EINVAL, "empty or null batch");
     mcpd_run_opts opts;
     if (opts_in) opts = *opts_in; else mcpd_run_opts_init(&opts);
-    if (opts.slot_nstar || opts.slot_units || opts.bucket_sum || opts.bucket_sumsq)
+    if (opts.slot_nstar || opts.slot_units || opts.bucket_sum || opts.bucket_sumsq || opts.mismatch)
         return fail(MCPD_EINVAL, "batch runs take no per-run output pointers in opts");
     std::vector<Item> items((size_t)count);
     bool wide = false;
@@ -1522,6 +1534,15 @@ int mcpd_batch_buckets(const mcpd_batch *b, int32_t index, uint32_t rows, int64_
     if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
     if (index < 0 || (size_t)index >= b->L->items.size()) return fail(MCPD_EINVAL, "index out of range");
     return copy_buckets(*b->L, (size_t)index, rows, sum, sumsq);
+}
+
+int mcpd_batch_mismatch(const mcpd_batch *b, int32_t index, uint64_t *out)
+{
+    using namespace mcpd::host;
+    if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
+    if (index < 0 || (size_t)index >= b->L->items.size()) return fail(MCPD_EINVAL, "index out of range");
+    if (!out) return fail(MCPD_EINVAL, "out is null");
+    return copy_mismatch(*b->L, (size_t)index, out);
 }
 
 int mcpd_batch_slot_records(mcpd_batch *b, int32_t index, uint32_t *nstar, uint64_t *units)

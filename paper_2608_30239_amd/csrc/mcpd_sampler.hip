@@ -48,6 +48,15 @@
 // draws with negated contributions.  At the end of a slot its numerators are
 // added to integer buckets keyed by N*_p, which makes the
 // completion-time-corrected aggregate exact and order-independent.
+//
+// Mismatch time: for each clone, D_j = #{s = 1..C : x_j(s) != y_j(s-1)},
+// summed over retained replications (where a pair's time apart goes, clone
+// by clone).  By summation by parts D_j = (C+1)|Delta_j(C)| - sum_u u e_u,
+// with e_u = |Delta_j(u)| - |Delta_j(u-1)| the change at time index u, so a
+// draw at t that changes |Delta_I| by e adds -(t+1) e, and a pair stopped by
+// the cap adds C+1 for every clone still apart.  The events are rare (they
+// only happen before the meeting) and go straight to the instance's output
+// with device-scope atomics; a rolled-back replication's replay cancels them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -230,6 +239,12 @@ struct Sampler {
         s.lim = lim;
     }
 
+    // Mismatch-time event of clone j (sign of the replication applied).
+    __device__ __forceinline__ void mismatch_event(int32_t sgn, uint32_t j, uint64_t v) const
+    {
+        atomicAdd(reinterpret_cast<unsigned long long *>(D->Dmis + j), (unsigned long long)(sgn > 0 ? v : (uint64_t)0 - v));
+    }
+
     __device__ __forceinline__ void spill(Lane &s, uint32_t j, uint64_t v) const
     {
         __hip_atomic_fetch_add(reinterpret_cast<uint64_t *>(acc + j), v, __ATOMIC_RELAXED,
@@ -373,7 +388,11 @@ struct Sampler {
                 if constexpr (SL) atomicAdd(&cnt(j >> 1), delta);   // LDS, no return
                 else cnt(j >> 1) += delta;
             }
-            if (s.tau == 0u) s.mu += (int)(xn != yn) - (int)(xi != yi);
+            if (s.tau == 0u) {
+                const int dmu = (int)(xn != yn) - (int)(xi != yi);
+                s.mu += dmu;
+                if (dmu != 0) mismatch_event(s.sgn, I, (uint64_t)(int64_t)(-dmu) * (uint64_t)(t + 1u));
+            }
             // estimator events at time te = t + 1
             uint64_t val = 0;
             const uint32_t te = t + 1u;
@@ -404,6 +423,7 @@ struct Sampler {
                 const uint32_t j = w * 16u + (b >> 1);
                 const uint64_t v = ((word >> b) & 1u) ? G : (uint64_t)0 - G;
                 event(s, j, s.sgn > 0 ? v : (uint64_t)0 - v);
+                mismatch_event(s.sgn, j, (uint64_t)C + 1u);
             }
         }
     }
@@ -930,6 +950,12 @@ struct Coop {
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
+    // Mismatch-time event of clone j (sign of the replication applied).
+    __device__ __forceinline__ void mismatch_event(int32_t sgn, uint32_t j, uint64_t v) const
+    {
+        atomicAdd(reinterpret_cast<unsigned long long *>(D->Dmis + j), (unsigned long long)(sgn > 0 ? v : (uint64_t)0 - v));
+    }
+
     __device__ __forceinline__ void add(uint32_t j, uint64_t v) const
     {
         __hip_atomic_fetch_add(reinterpret_cast<uint64_t *>(acc + j), v, __ATOMIC_RELAXED,
@@ -1017,6 +1043,7 @@ struct Coop {
                 mis &= mis - 1u;
                 const uint64_t v = ((word >> b) & 1u) ? G : (uint64_t)0 - G;
                 add(w * 16u + (b >> 1), s.sgn > 0 ? v : (uint64_t)0 - v);
+                mismatch_event(s.sgn, w * 16u + (b >> 1), (uint64_t)C + 1u);
             }
         }
         s.lc = a.list_cap + 1u;
@@ -1223,6 +1250,7 @@ struct Coop {
             }
             int dmu = 0;
             if (s.tau == 0u) dmu = (int)(xn != yn) - (int)(xi != yi);
+            if (dmu != 0) mismatch_event(s.sgn, I, (uint64_t)(int64_t)(-dmu) * (uint64_t)(t + 1u));
             uint64_t val = 0;
             const uint32_t te = t + 1u;
             if (dx != 0 && te <= D->ell) {

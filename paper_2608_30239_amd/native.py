@@ -55,6 +55,7 @@ class RunOpts(C.Structure):
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),
         ("bucket_sumsq", C.c_void_p),
+        ("mismatch", C.c_void_p),
     ]
 
 
@@ -91,7 +92,7 @@ EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_prune", "mcpd_creat
            "mcpd_get_weights", "mcpd_run_unbiased", "mcpd_run_unbiased_dev", "mcpd_run_unbiased_dev_noalloc",
            "mcpd_destroy", "mcpd_batch_create",
            "mcpd_batch_run", "mcpd_batch_tune", "mcpd_batch_config", "mcpd_batch_buckets",
-           "mcpd_batch_slot_records", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_features",
+           "mcpd_batch_slot_records", "mcpd_batch_mismatch", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_features",
            "mcpd_mlp_create", "mcpd_mlp_get_params", "mcpd_mlp_set_params", "mcpd_mlp_forward",
            "mcpd_mlp_set_training_rows", "mcpd_mlp_set_training_data", "mcpd_mlp_loss_grad",
            "mcpd_mlp_train", "mcpd_set_learned_weights", "mcpd_mlp_destroy", "mcpd_probe", "mcpd_strerror",
@@ -152,6 +153,7 @@ def load(path: Optional[str] = None):
         L.mcpd_batch_config.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mcpd_batch_buckets.argtypes = [vp, C.c_int32, C.c_uint32, vp, vp]
         L.mcpd_batch_slot_records.argtypes = [vp, C.c_int32, vp, vp]
+        L.mcpd_batch_mismatch.argtypes = [vp, C.c_int32, vp]
         L.mcpd_batch_destroy.argtypes = [vp]
         L.mcpd_batch_destroy.restype = None
         L.mcpd_run_batch.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_uint64, C.POINTER(RunOpts), vp, vp,
@@ -239,11 +241,17 @@ def run_opts(**kw) -> RunOpts:
     return o
 
 
-def mcpd_run_unbiased(h, n, budget, slots, k, m, seed=0, slot_records=False, buckets=0, **opt):
-    """Returns dict(marginals, stderr, hist, stats[, slot_nstar, slot_units, bucket_sum, bucket_sumsq])."""
+def mcpd_run_unbiased(h, n, budget, slots, k, m, seed=0, slot_records=False, buckets=0, mismatch=False, **opt):
+    """Returns dict(marginals, stderr, hist, stats[, slot_nstar, slot_units, bucket_sum, bucket_sumsq,
+    mismatch])."""
     o = run_opts(**opt)
     out = {}
     keep = []
+    if mismatch:
+        mis = np.zeros(n, np.uint64)
+        o.mismatch = _p(mis).value
+        out.update(mismatch=mis)
+        keep.append(mis)
     if slot_records:
         ns = np.zeros(slots, np.uint32)
         su = np.zeros(slots, np.uint64)
@@ -365,6 +373,12 @@ class Batch:
         b2 = np.zeros((rows, n, 2), np.uint64)
         _check(load().mcpd_batch_buckets(self.h, i, rows, _p(b1), _p(b2)), "mcpd_batch_buckets")
         return b1, b2
+
+    def mismatch(self, i):
+        """Mismatch times of instance i of the last run (n values)."""
+        out = np.zeros(self.decoders[i].n, np.uint64)
+        _check(load().mcpd_batch_mismatch(self.h, i, _p(out)), "mcpd_batch_mismatch")
+        return out
 
     def slot_records(self, i):
         P = int(self.slots[i])

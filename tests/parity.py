@@ -1,10 +1,11 @@
 """Shared comparison of a GPU result with the oracle's (GPU tests only).
 
 Integer results (N* buckets of the exact numerators, sums of squares,
-meeting-time histograms, per-slot N* and S_p, retained-pair counters) must be
-bit-identical.  The FP64 marginals and standard errors are formed on each
-side from those integers in a different order (the oracle averages slot
-means in slot order, the library divides the per-N* sums): they must agree
+meeting-time histograms, per-clone mismatch times, per-slot N* and S_p,
+retained-pair counters) must be bit-identical.  The FP64 marginals and
+standard errors are formed on each side from those integers in a different
+order (the oracle averages slot means in slot order, the library divides the
+per-N* sums): they must agree
 within 1e-12 relative to the scale of the estimates (standard errors within
 1e-10, since they pass through a difference of sums of squares).
 
@@ -97,6 +98,8 @@ def check(gpu, orc, budget, slots, m, tol=1e-12):
     assert np.array_equal(gpu["bucket_sum"], orc["bucket1"])
     assert np.array_equal(gpu["bucket_sumsq"], orc["bucket2"])
     assert np.array_equal(gpu["hist"], orc["hist"])
+    if "mismatch" in gpu:
+        assert np.array_equal(gpu["mismatch"], orc["mismatch"])
     if "slot_nstar" in gpu:
         assert np.array_equal(gpu["slot_nstar"], orc["slot_nstar"])
         assert np.array_equal(gpu["slot_units"], orc["slot_sret"])

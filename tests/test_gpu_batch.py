@@ -49,7 +49,7 @@ def run_batch(spec, seed, runs=1, **opt):
         for i, (inst, budget, slots, k, m) in enumerate(spec):
             nb = max(1, (budget // slots) // max(m, 1))
             b1, b2 = bt.buckets(i, nb)
-            outs[-1][i].update(bucket_sum=b1, bucket_sumsq=b2)
+            outs[-1][i].update(bucket_sum=b1, bucket_sumsq=b2, mismatch=bt.mismatch(i))
             if opt.get("keep_slot_records"):
                 ns, su = bt.slot_records(i)
                 outs[-1][i].update(slot_nstar=ns, slot_units=su)

@@ -34,7 +34,7 @@ def compare(inst, budget, slots, k, m, seed=0, weights=None, tol=1e-12, **opt):
             dec.set_weights(weights)
         w_exact, mass = dec.weights()
         assert np.array_equal(mass, orc["masses"])
-        gpu = dec.run(budget, slots, k, m, seed, slot_records=True, buckets=nb, **opt)
+        gpu = dec.run(budget, slots, k, m, seed, slot_records=True, buckets=nb, mismatch=True, **opt)
     finally:
         dec.close()
     P.check(gpu, orc, budget, slots, m, tol)

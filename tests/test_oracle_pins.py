@@ -357,6 +357,51 @@ def test_coupling_faithful_and_cost():
             assert len(diff) <= 1 and (len(diff) == 0 or diff[0] == tr["I"][t])
 
 
+def literal_mismatch(tr):
+    """Mismatch time of every clone, from the stored paths: the number of
+    time indices s = 1..C at which x_j(s) != y_j(s-1)."""
+    X, Y, C = tr["X"], tr["Y"], tr["C"]
+    return [int(sum(int(X[s][j] != Y[s - 1][j]) for s in range(1, C + 1))) for j in range(X.shape[1])]
+
+
+def test_mismatch_time_equals_literal_count():
+    """Met pairs (the count stops at the meeting) and pairs stopped by the
+    cap (the count runs to C), both initial distributions."""
+    inst = twelve_clone_instance(seed=3, fp=0.2, fn=0.2, q=0.3)
+    M = O.Model(inst)
+    seen_long = seen_cap = 0
+    for init_mode in (0, 1):
+        for p in range(40):
+            for cap in (0, 9):
+                tr = M.trace(p, 1, max_len=20000, k=2, m=6, budget=0, slots=1, seed=5, max_steps=cap,
+                             init_mode=init_mode)
+                lit = literal_mismatch(tr)
+                assert list(tr["mismatch"]) == lit
+                seen_cap += tr["capped"]
+                seen_long += sum(lit) > 3
+                if not tr["capped"]:
+                    # the total over clones is the summed size of the mismatch set before tau
+                    X, Y = tr["X"], tr["Y"]
+                    assert sum(lit) == sum(int((X[s] != Y[s - 1]).sum()) for s in range(1, tr["tau"]))
+    assert seen_cap > 0 and seen_long > 0
+
+
+def test_run_mismatch_is_sum_over_retained_replications():
+    inst, rp = I.tiny_plain()
+    M = O.Model(inst)
+    k, ell, seed, slots, B = 3, 20, 7, 24, 50
+    res = M.run(B * slots, slots, k, ell, seed=seed, slot_records=True)
+    want = np.zeros(inst.n, np.int64)
+    for p in range(slots):
+        for r in range(1, int(res["slot_nstar"][p]) + 1):
+            want += M.trace(p, r, max_len=200000, k=k, m=ell, budget=0, slots=1, seed=seed)["mismatch"]
+    assert list(res["mismatch"].astype(np.int64)) == list(want)
+    assert want.sum() > 0
+    # the thread count does not change it
+    res1 = M.run(B * slots, slots, k, ell, seed=seed, nthreads=1)
+    assert np.array_equal(res1["mismatch"], res["mismatch"])
+
+
 # --------------------------------------------------------------------------
 # Unbiasedness against exact marginals
 # --------------------------------------------------------------------------
