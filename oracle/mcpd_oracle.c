@@ -31,6 +31,8 @@
  * Trajectory bits themselves have no printed worked example in the paper:
  * beyond the pins above they are parity unpinned.
  */
+#include "mcpd_oracle.h"
+
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -124,7 +126,7 @@ void mo_draw(uint64_t seed, uint32_t g, uint32_t p, uint32_t r, uint64_t t, uint
  * xi_j(z) = 1{sum_i A_ji z_i > 0}.  Observation channel (reading; the paper
  * names only the two rates): Pr{y=1|xi=1} = 1-fn, Pr{y=1|xi=0} = fp.
  * ---------------------------------------------------------------------- */
-typedef struct {
+typedef struct mo_model {
     int32_t n, m;
     int32_t *row_ptr;   /* n+1 */
     int32_t *pool_idx;  /* nnz, ascending per row */
@@ -990,3 +992,117 @@ int mo_slot(const mo_model *M, const mo_params *P, uint32_t p, int64_t *numer, u
     scratch_free(&s);
     return rc;
 }
+
+
+/* ------------------------------------------------------------------------
+ * The same entry points in the shape of the library's C ABI (declared in
+ * mcpd_oracle.h): thin wrappers over the functions above.
+ * ---------------------------------------------------------------------- */
+void mcpd_oracle_opts_init(mcpd_oracle_opts *o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->refill = 1;
+    o->hist_bins = 64;
+    o->u_hi_bits = 32;
+}
+
+int mcpd_oracle_create(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *pool_idx, const uint8_t *y,
+                       double fp, double fn, double prior, mcpd_oracle_instance **out)
+{
+    if (!out) return MO_EINVAL;
+    *out = NULL;
+    if (!row_ptr || !pool_idx || !y) return MO_EINVAL;
+    mo_model *M = mo_model_create(n, m, row_ptr, pool_idx, y, fp, fn, prior, NULL);
+    if (!M) return MO_EINVAL;
+    *out = M;
+    return MO_OK;
+}
+
+int mcpd_oracle_set_weights(mcpd_oracle_instance *M, const double *w)
+{
+    if (!M) return MO_EINVAL;
+    double *nw = (double *)malloc((size_t)M->n * sizeof(double));
+    double *s = (double *)malloc((size_t)M->n * sizeof(double));
+    uint64_t *mass = (uint64_t *)malloc((size_t)M->n * sizeof(uint64_t));
+    int rc = (nw && s && mass) ? MO_OK : MO_ENOMEM;
+    if (!rc) {
+        if (w) memcpy(nw, w, (size_t)M->n * sizeof(double));
+        else rc = mo_score_weights(M->n, M->m, M->row_ptr, M->pool_idx, M->y, M->fp, M->fn, M->q, s, nw);
+    }
+    if (!rc) rc = mo_quantize(M->n, nw, mass);
+    if (!rc) {
+        memcpy(M->w, nw, (size_t)M->n * sizeof(double));
+        memcpy(M->mass, mass, (size_t)M->n * sizeof(uint64_t));
+        free(M->athr);
+        free(M->alias);
+        M->athr = NULL;
+        M->alias = NULL;
+        rc = build_alias(M);
+    }
+    free(nw); free(s); free(mass);
+    return rc;
+}
+
+int mcpd_oracle_get_weights(const mcpd_oracle_instance *M, double *w_exact, uint64_t *mass)
+{
+    if (!M) return MO_EINVAL;
+    for (int32_t i = 0; i < M->n; ++i) {
+        if (w_exact) w_exact[i] = (double)M->mass[i] / 4294967296.0;
+        if (mass) mass[i] = M->mass[i];
+    }
+    return MO_OK;
+}
+
+static void params_from(const mcpd_oracle_instance *M, const mcpd_oracle_opts *o, uint64_t budget, uint32_t slots,
+                        uint32_t k, uint32_t m, uint64_t seed, mo_params *P)
+{
+    mcpd_oracle_opts d;
+    if (!o) { mcpd_oracle_opts_init(&d); o = &d; }
+    P->budget = budget; P->slots = slots; P->k = k; P->ell = m; P->seed = seed;
+    P->max_steps = o->max_steps; P->refill = o->refill; P->hist_bins = o->hist_bins;
+    P->hist_width = o->hist_width ? o->hist_width : (uint64_t)M->n;
+    P->u_hi_bits = o->u_hi_bits; P->instance_id = o->instance_id; P->init_mode = o->init_mode;
+}
+
+int mcpd_oracle_run_unbiased(mcpd_oracle_instance *M, uint64_t budget, uint32_t slots, uint32_t k, uint32_t m,
+                             uint64_t seed, const mcpd_oracle_opts *o, double *marginals, double *stderr_out,
+                             uint64_t *hist, mcpd_oracle_stats *stats)
+{
+    if (!M || !marginals || !stderr_out || !hist) return MO_EINVAL;
+    mo_params P;
+    params_from(M, o, budget, slots, k, m, seed, &P);
+    uint64_t st[ST_COUNT];
+    int rc = mo_run(M, &P, marginals, stderr_out, hist, st, o ? o->slot_nstar : NULL, o ? o->slot_units : NULL, NULL,
+                    o ? o->bucket_sum : NULL, o ? o->bucket_sumsq : NULL, o ? o->bucket_rows : 0,
+                    o ? o->mismatch : NULL, o ? o->nthreads : 0);
+    if (!rc && stats) {
+        stats->retained_units = st[ST_RETAINED_UNITS];
+        stats->single_site_updates = st[ST_SINGLE_SITE];
+        stats->reps_retained = st[ST_REPS_RETAINED];
+        stats->cap_hits = st[ST_CAP_HITS];
+        stats->zero_completion_slots = st[ST_ZERO_COMPLETION];
+        stats->tau_sum = st[ST_TAU_SUM];
+        stats->tau_max = st[ST_TAU_MAX];
+        stats->reps_discarded = st[ST_REPS_DISCARDED];
+        stats->discarded_units = st[ST_DISCARDED_UNITS];
+        stats->nstar_max = st[ST_NSTAR_MAX];
+    }
+    return rc;
+}
+
+int mcpd_oracle_trace(mcpd_oracle_instance *M, uint32_t slot, uint32_t r, uint64_t seed, uint32_t k, uint32_t m,
+                      const mcpd_oracle_opts *o, uint64_t max_len, uint8_t *X, uint8_t *Y, int32_t *I, uint64_t *U,
+                      int64_t *numer, int64_t *mismatch, uint64_t out[3])
+{
+    if (!M || !X || !Y || !I || !U || !out || r < 1) return MO_EINVAL;
+    mo_params P;
+    params_from(M, o, 0, 1, k, m, seed, &P);
+    int64_t *nbuf = numer ? numer : (int64_t *)malloc((size_t)M->n * sizeof(int64_t));
+    if (!nbuf) return MO_ENOMEM;
+    int rc = mo_trace(M, &P, slot, r, max_len, X, Y, I, U, nbuf, mismatch, out);
+    if (!numer) free(nbuf);
+    return rc;
+}
+
+void mcpd_oracle_destroy(mcpd_oracle_instance *M) { mo_model_free(M); }
