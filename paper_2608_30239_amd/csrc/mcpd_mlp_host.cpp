@@ -348,6 +348,80 @@ int mcpd_mlp_train(mcpd_mlp *M, int32_t steps, const mcpd_adamw *hp, double *los
     return MCPD_OK;
 }
 
+int mcpd_mlp_backward(mcpd_mlp *M, const float *x, int64_t rows, const float *dg, float *grad)
+{
+    if (!M || !x || !dg || !grad || rows <= 0) return fail(MCPD_EINVAL, "bad argument");
+    int64_t per = 0;
+    const int nblocks = K::backward_blocks(rows, M->cus, &per);
+    float *dX = nullptr, *ddg = nullptr, *dpart = nullptr, *dgrad = nullptr;
+    int rc = dev_alloc(&dX, (size_t)rows * MCPD_MLP_FEATURES);
+    if (!rc) rc = dev_alloc(&ddg, (size_t)rows);
+    if (!rc) rc = dev_alloc(&dpart, (size_t)nblocks * MCPD_MLP_PARAMS);
+    if (!rc) rc = dev_alloc(&dgrad, (size_t)MCPD_MLP_PARAMS);
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(dX, x, (size_t)rows * MCPD_MLP_FEATURES * 4, hipMemcpyHostToDevice, M->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(ddg, dg, (size_t)rows * 4, hipMemcpyHostToDevice, M->stream);
+        if (e == hipSuccess)
+            e = (hipError_t)K::launch_backward(M->d_wb, dX, ddg, rows, nblocks, per, dpart, dgrad, M->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(grad, dgrad, MCPD_MLP_PARAMS * 4, hipMemcpyDeviceToHost, M->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(M->stream);
+        if (e != hipSuccess) rc = hip_fail(e, "backward");
+    }
+    dev_free(dX);
+    dev_free(ddg);
+    dev_free(dpart);
+    dev_free(dgrad);
+    return rc;
+}
+
+int mcpd_mlp_adamw_step(mcpd_mlp *M, const float *grad, const mcpd_adamw *hp)
+{
+    if (!M || !grad || !hp) return fail(MCPD_EINVAL, "bad argument");
+    if (!(hp->lr > 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) ||
+        !(hp->eps > 0.f) || !(hp->weight_decay >= 0.f))
+        return fail(MCPD_EINVAL, "bad AdamW hyper-parameters");
+    if (!finite_params(grad)) return fail(MCPD_EINVAL, "gradient must be finite");
+    HIP_TRY(hipMemcpyAsync(M->d_grad, grad, MCPD_MLP_PARAMS * 4, hipMemcpyHostToDevice, M->stream));
+    M->step += 1;
+    const double bc1 = 1.0 - std::pow((double)hp->beta1, (double)M->step);
+    const double bc2 = 1.0 - std::pow((double)hp->beta2, (double)M->step);
+    int e = K::launch_adamw(M->d_theta, M->d_m, M->d_v, M->d_grad, M->d_wb, hp->lr, hp->beta1, hp->beta2, hp->eps,
+                            hp->weight_decay, (float)bc1, (float)bc2, M->stream);
+    if (e != hipSuccess) return hip_fail((hipError_t)e, "adamw kernel");
+    HIP_TRY(hipStreamSynchronize(M->stream));
+    return MCPD_OK;
+}
+
+int mcpd_mlp_get_state(const mcpd_mlp *M, float *master, uint16_t *bf16, float *adam_m, float *adam_v, int64_t *step)
+{
+    if (!M) return fail(MCPD_EINVAL, "null network");
+    if (master) HIP_TRY(hipMemcpyAsync(master, M->d_theta, MCPD_MLP_PARAMS * 4, hipMemcpyDeviceToHost, M->stream));
+    if (bf16) HIP_TRY(hipMemcpyAsync(bf16, M->d_wb, MCPD_MLP_PARAMS * 2, hipMemcpyDeviceToHost, M->stream));
+    if (adam_m) HIP_TRY(hipMemcpyAsync(adam_m, M->d_m, MCPD_MLP_PARAMS * 4, hipMemcpyDeviceToHost, M->stream));
+    if (adam_v) HIP_TRY(hipMemcpyAsync(adam_v, M->d_v, MCPD_MLP_PARAMS * 4, hipMemcpyDeviceToHost, M->stream));
+    HIP_TRY(hipStreamSynchronize(M->stream));
+    if (step) *step = M->step;
+    return MCPD_OK;
+}
+
+int mcpd_mlp_set_state(mcpd_mlp *M, const float *master, const float *adam_m, const float *adam_v, int64_t step)
+{
+    if (!M) return fail(MCPD_EINVAL, "null network");
+    if (!master || !adam_m || !adam_v || step < 0) return fail(MCPD_EINVAL, "bad argument");
+    if (!finite_params(master) || !finite_params(adam_m) || !finite_params(adam_v))
+        return fail(MCPD_EINVAL, "state must be finite");
+    for (int k = 0; k < MCPD_MLP_PARAMS; ++k)
+        if (adam_v[k] < 0.f) return fail(MCPD_EINVAL, "second moments must be >= 0");
+    HIP_TRY(hipMemcpyAsync(M->d_theta, master, MCPD_MLP_PARAMS * 4, hipMemcpyHostToDevice, M->stream));
+    HIP_TRY(hipMemcpyAsync(M->d_m, adam_m, MCPD_MLP_PARAMS * 4, hipMemcpyHostToDevice, M->stream));
+    HIP_TRY(hipMemcpyAsync(M->d_v, adam_v, MCPD_MLP_PARAMS * 4, hipMemcpyHostToDevice, M->stream));
+    int e = K::launch_cast(M->d_theta, M->d_wb, M->stream);
+    if (e != hipSuccess) return hip_fail((hipError_t)e, "cast kernel");
+    HIP_TRY(hipStreamSynchronize(M->stream));
+    M->step = step;
+    return MCPD_OK;
+}
+
 int mcpd_set_learned_weights(mcpd_instance *I, mcpd_mlp *M, double alpha, double *w_out)
 {
     if (!I || !M) return fail(MCPD_EINVAL, "null argument");

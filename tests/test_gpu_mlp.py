@@ -189,3 +189,83 @@ def test_zero_network_gives_back_the_score_weights(make):
     _, ws = O.score_weights(inst)
     assert np.array_equal(w, ws)
     assert np.array_equal(mass, score_mass)
+
+
+def test_backward_entry_point_matches_oracle():
+    theta = I.mlp_init(11)
+    X, base, signal, seg = _training_rows(seed=12)
+    rng = np.random.default_rng(13)
+    dg = rng.normal(size=X.shape[0]).astype(np.float32)
+    net = N.Mlp(theta)
+    try:
+        grad = net.backward(X, dg)
+    finally:
+        net.close()
+    ref = MO.backward(MO.bf16_round(theta).astype(np.float64), X.astype(np.float64), dg.astype(np.float64))
+    assert np.max(np.abs(grad - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+def test_adamw_step_entry_point_equals_fused_training_step():
+    """loss_grad then adamw_step gives the state train(1) gives, bit for
+    bit, and the step follows the closed form."""
+    theta = I.mlp_init(14)
+    X, base, signal, seg = _training_rows(seed=15)
+    hp = dict(lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-6, weight_decay=0.05)
+    a, b = N.Mlp(theta), N.Mlp(theta)
+    try:
+        for net in (a, b):
+            net.set_training_rows(X, base, signal, seg, 0.75, 0.5, 1e-2)
+        th = theta.astype(np.float64)
+        m = np.zeros_like(th)
+        v = np.zeros_like(th)
+        for step in (1, 2):
+            _, grad = a.loss_grad()
+            a.adamw_step(grad, **hp)
+            b.train(1, **hp)
+            sa, sb = a.state(), b.state()
+            for x, y in zip(sa[:4], sb[:4]):
+                assert np.array_equal(x, y)
+            assert sa[4] == sb[4] == step
+            th, m, v = MO.adamw_step(th, m, v, grad.astype(np.float64), step, hp["lr"], hp["beta1"], hp["beta2"],
+                                     hp["eps"], hp["weight_decay"])
+            assert np.max(np.abs(sa[0] - th)) <= 1e-6 * (1 + np.max(np.abs(th)))
+            th = sa[0].astype(np.float64)
+        with pytest.raises(N.McpdError):
+            a.adamw_step(np.full(N.MLP_PARAMS, np.nan, np.float32), **hp)
+    finally:
+        a.close()
+        b.close()
+
+
+def test_checkpoint_resume_continues_bit_for_bit(tmp_path):
+    """Train, save the whole optimiser state, restore it into a new network
+    and train both on: master, BF16 copy, moments and step stay identical."""
+    from paper_2608_30239_amd import selection as S
+    theta = I.mlp_init(16)
+    X, base, signal, seg = _training_rows(seed=17, sizes=(300, 500, 700))
+    hp = dict(lr=3e-3, weight_decay=1e-4)
+    net = N.Mlp(theta)
+    path = str(tmp_path / "ckpt.npz")
+    try:
+        net.set_training_rows(X, base, signal, seg, 0.7, 0.3, 1e-3)
+        net.train(7, **hp)
+        S.save_checkpoint(net, path, note="after 7 steps")
+        back = S.load_checkpoint(path)
+        try:
+            assert back.state()[4] == 7
+            back.set_training_rows(X, base, signal, seg, 0.7, 0.3, 1e-3)
+            h1 = net.train(5, **hp)
+            h2 = back.train(5, **hp)
+            assert np.array_equal(h1, h2)
+            for x, y in zip(net.state(), back.state()):
+                assert np.array_equal(x, y)
+        finally:
+            back.close()
+        # a damaged checkpoint is refused
+        z = dict(np.load(path, allow_pickle=False))
+        z["adam_m"] = z["adam_m"] + np.float32(1e-3)
+        np.savez(path, **z)
+        with pytest.raises(ValueError, match="hash"):
+            S.load_checkpoint(path)
+    finally:
+        net.close()
