@@ -194,20 +194,23 @@ def batch_lines(steps: int):
 
 
 def learned_line(nref: int, nrep: int):
-    """Learned against score weights on the paper-shaped workload."""
-    from paper_2608_30239_amd import instances as I
+    """Learned against score weights at equal budget on the five held-out
+    evaluation instances (the paper-shaped one and four with 20000 clones),
+    each with a bootstrap interval of the gain."""
     from paper_2608_30239_amd import native as N
     from paper_2608_30239_amd import selection as S
     params, rep = S.load_trained()
     net = N.Mlp(params)
     try:
-        res = S.evaluate(net, nref=nref, nrep=nrep, instances=[I.paper_shaped()], log=lambda m: None)
+        res = S.evaluate(net, nref=nref, nrep=nrep, log=lambda m: None)
     finally:
         net.close()
-    row = res["rows"][0]
-    keep = ("rmse_score", "rmse_learned", "seconds_score", "seconds_learned", "gain", "var_gain")
-    return dict({k: row[k] for k in keep}, reference_runs=nref, runs=nrep,
-                metric="efficiency 1/(MSE x device seconds), learned over score weights")
+    keep = ("rmse_score", "rmse_learned", "seconds_score", "seconds_learned", "gain", "gain_ci90", "median_gain",
+            "var_gain", "tau_max_p99")
+    return dict(instances={r["instance"]: {k: r[k] for k in keep} for r in res["rows"]},
+                gain_geomean=res["gain_geomean"], median_gain_geomean=res["median_gain_geomean"],
+                reference_runs=nref, runs=nrep,
+                metric="efficiency 1/(MSE x device seconds), learned over score weights; 90% bootstrap interval")
 
 
 def copy_calibration(mib: int, reps: int):
@@ -332,7 +335,7 @@ def main():
     if not args.no_batches:
         out["batches"] = batch_lines(3)
     if not args.no_learned:
-        out["learned_vs_score"] = learned_line(16, 8)
+        out["learned_vs_score"] = learned_line(384, 384)
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(inst, rp, threads)

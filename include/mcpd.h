@@ -112,6 +112,12 @@ typedef struct mcpd_run_opts {
                                up exactly to the whole run's; slot records
                                are indexed from the first slot;
                                MCPD_EINVAL if first_slot + slots > 2^32     */
+    uint32_t keep_mismatch; /* batches: count the mismatch times of every
+                               instance for mcpd_batch_mismatch (single runs
+                               count them when `mismatch` is given); off by
+                               default, since their events cost device-wide
+                               atomics on the few clones most pairs disagree on */
+    uint32_t reserved0;     /* set to 0                                        */
     /* Optional host outputs of mcpd_run_unbiased (NULL = not wanted; must be
        NULL for batches). */
     uint32_t *slot_nstar;   /* [slots] N*_p(B)                                 */
@@ -353,7 +359,8 @@ int mcpd_batch_buckets(const mcpd_batch *batch, int32_t index, uint32_t rows, in
 int mcpd_batch_slot_records(mcpd_batch *batch, int32_t index, uint32_t *nstar, uint64_t *units);
 
 /* Mismatch times of instance `index` of the last batch run (host, n values;
- * as mcpd_run_opts.mismatch).  Errors: MCPD_EINVAL (null, index out of range). */
+ * as mcpd_run_opts.mismatch).  Needs opts.keep_mismatch at creation.
+ * Errors: MCPD_EINVAL (null, index out of range, not kept). */
 int mcpd_batch_mismatch(const mcpd_batch *batch, int32_t index, uint64_t *out);
 
 /* Release a batch (NULL is a no-op); the instances stay. */
@@ -444,6 +451,30 @@ int mcpd_mlp_loss_grad(mcpd_mlp *mlp, double *loss, float *grad);
  * loss before each step.  The step counter of the bias corrections
  * continues across calls until mcpd_mlp_set_params. */
 int mcpd_mlp_train(mcpd_mlp *mlp, int32_t steps, const mcpd_adamw *hp, double *loss_history);
+
+/* Gradient in the parameters (host [MCPD_MLP_PARAMS]) of sum_r dg[r] g_r
+ * over `rows` rows of features x (host [rows * 8]) with the upstream
+ * derivatives dg (host [rows]), through the BF16 working copy (the
+ * straight-through gradient the FP32 master receives): the backward pass
+ * alone, on the device.  Errors: MCPD_EINVAL, MCPD_ENOMEM, MCPD_EDEVICE. */
+int mcpd_mlp_backward(mcpd_mlp *mlp, const float *x, int64_t rows, const float *dg, float *grad);
+
+/* One AdamW step with decoupled weight decay on every parameter, with the
+ * given gradient (host [MCPD_MLP_PARAMS], finite), on the device: moments,
+ * bias corrections from the step counter (which it advances), FP32 master
+ * update and the BF16 copy.  Errors: MCPD_EINVAL, MCPD_EDEVICE. */
+int mcpd_mlp_adamw_step(mcpd_mlp *mlp, const float *grad, const mcpd_adamw *hp);
+
+/* Optimiser state for checkpoints: FP32 master parameters, their BF16 copy,
+ * the AdamW first and second moments (host [MCPD_MLP_PARAMS] each; any may be
+ * NULL) and the step counter.  set_state restores master, moments and step
+ * and rebuilds the BF16 copy from the master (round to nearest even), so a
+ * restored network continues training exactly as the saved one would.
+ * Errors: MCPD_EINVAL (null or non-finite state, negative second moment or
+ * step), MCPD_EDEVICE. */
+int mcpd_mlp_get_state(const mcpd_mlp *mlp, float *master, uint16_t *bf16, float *adam_m, float *adam_v,
+                       int64_t *step);
+int mcpd_mlp_set_state(mcpd_mlp *mlp, const float *master, const float *adam_m, const float *adam_v, int64_t step);
 
 /* Set an instance's selection weights from the network: features, base
  * logits and network outputs on the device, then w = (1 - alpha)

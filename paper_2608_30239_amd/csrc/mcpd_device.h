@@ -130,6 +130,7 @@ struct LaunchArgs {
     uint32_t gwords;            // >= every global-state instance's words_bits + words_cnt
     uint32_t group_log2;        // cooperative kernel: log2 of the lanes that run one slot (3..6)
     uint32_t init_mode;         // 0: all-negative initial state; 1: drawn from the prior
+    uint32_t mismatch;          // 1: count the mismatch times (Dmis of each instance)
     const uint64_t *seed;       // device copy of the 64-bit key
     int64_t *acc;               // [lanes * acc_stride] spilled numerators (kept zero between slots)
     uint32_t *lists;            // [lanes * list_cap]

@@ -862,6 +862,7 @@ LaunchArgs launch_args(const Launch &L)
     a.gwords = L.gwords;
     a.group_log2 = L.cfg.group_log2;
     a.init_mode = L.opts.init_mode;
+    a.mismatch = (L.opts.keep_mismatch || L.opts.mismatch) ? 1u : 0u;
     a.seed = L.d_seed;
     a.acc = L.d_acc;
     a.lists = L.d_lists;
@@ -1542,6 +1543,7 @@ int mcpd_batch_mismatch(const mcpd_batch *b, int32_t index, uint64_t *out)
     if (!b || !b->L) return fail(MCPD_EINVAL, "null batch");
     if (index < 0 || (size_t)index >= b->L->items.size()) return fail(MCPD_EINVAL, "index out of range");
     if (!out) return fail(MCPD_EINVAL, "out is null");
+    if (!b->L->opts.keep_mismatch) return fail(MCPD_EINVAL, "mismatch times were not kept (keep_mismatch = 0)");
     return copy_mismatch(*b->L, (size_t)index, out);
 }
 

@@ -54,9 +54,11 @@
 // by clone).  By summation by parts D_j = (C+1)|Delta_j(C)| - sum_u u e_u,
 // with e_u = |Delta_j(u)| - |Delta_j(u-1)| the change at time index u, so a
 // draw at t that changes |Delta_I| by e adds -(t+1) e, and a pair stopped by
-// the cap adds C+1 for every clone still apart.  The events are rare (they
-// only happen before the meeting) and go straight to the instance's output
-// with device-scope atomics; a rolled-back replication's replay cancels them.
+// the cap adds C+1 for every clone still apart.  The events only happen
+// before the meeting and go straight to the instance's output with
+// device-scope atomics (a rolled-back replication's replay cancels them);
+// they are counted only when a run asks for them, since most pairs disagree
+// on the same few clones and those atomics then contend.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -391,7 +393,7 @@ struct Sampler {
             if (s.tau == 0u) {
                 const int dmu = (int)(xn != yn) - (int)(xi != yi);
                 s.mu += dmu;
-                if (dmu != 0) mismatch_event(s.sgn, I, (uint64_t)(int64_t)(-dmu) * (uint64_t)(t + 1u));
+                if (a.mismatch && dmu != 0) mismatch_event(s.sgn, I, (uint64_t)(int64_t)(-dmu) * (uint64_t)(t + 1u));
             }
             // estimator events at time te = t + 1
             uint64_t val = 0;
@@ -423,7 +425,7 @@ struct Sampler {
                 const uint32_t j = w * 16u + (b >> 1);
                 const uint64_t v = ((word >> b) & 1u) ? G : (uint64_t)0 - G;
                 event(s, j, s.sgn > 0 ? v : (uint64_t)0 - v);
-                mismatch_event(s.sgn, j, (uint64_t)C + 1u);
+                if (a.mismatch) mismatch_event(s.sgn, j, (uint64_t)C + 1u);
             }
         }
     }
@@ -1043,7 +1045,7 @@ struct Coop {
                 mis &= mis - 1u;
                 const uint64_t v = ((word >> b) & 1u) ? G : (uint64_t)0 - G;
                 add(w * 16u + (b >> 1), s.sgn > 0 ? v : (uint64_t)0 - v);
-                mismatch_event(s.sgn, w * 16u + (b >> 1), (uint64_t)C + 1u);
+                if (a.mismatch) mismatch_event(s.sgn, w * 16u + (b >> 1), (uint64_t)C + 1u);
             }
         }
         s.lc = a.list_cap + 1u;
@@ -1250,7 +1252,7 @@ struct Coop {
             }
             int dmu = 0;
             if (s.tau == 0u) dmu = (int)(xn != yn) - (int)(xi != yi);
-            if (dmu != 0) mismatch_event(s.sgn, I, (uint64_t)(int64_t)(-dmu) * (uint64_t)(t + 1u));
+            if (a.mismatch && dmu != 0) mismatch_event(s.sgn, I, (uint64_t)(int64_t)(-dmu) * (uint64_t)(t + 1u));
             uint64_t val = 0;
             const uint32_t te = t + 1u;
             if (dx != 0 && te <= D->ell) {

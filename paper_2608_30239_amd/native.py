@@ -51,6 +51,8 @@ class RunOpts(C.Structure):
         ("init_mode", C.c_uint32),
         ("cap_sweeps", C.c_uint32),
         ("first_slot", C.c_uint32),
+        ("keep_mismatch", C.c_uint32),
+        ("reserved0", C.c_uint32),
         ("slot_nstar", C.c_void_p),
         ("slot_units", C.c_void_p),
         ("bucket_sum", C.c_void_p),
@@ -95,7 +97,8 @@ EXPORTS = ("mcpd_run_opts_init", "mcpd_score_weights", "mcpd_prune", "mcpd_creat
            "mcpd_batch_slot_records", "mcpd_batch_mismatch", "mcpd_batch_destroy", "mcpd_run_batch", "mcpd_features",
            "mcpd_mlp_create", "mcpd_mlp_get_params", "mcpd_mlp_set_params", "mcpd_mlp_forward",
            "mcpd_mlp_set_training_rows", "mcpd_mlp_set_training_data", "mcpd_mlp_loss_grad",
-           "mcpd_mlp_train", "mcpd_set_learned_weights", "mcpd_mlp_destroy", "mcpd_probe", "mcpd_strerror",
+           "mcpd_mlp_train", "mcpd_mlp_backward", "mcpd_mlp_adamw_step", "mcpd_mlp_get_state", "mcpd_mlp_set_state",
+           "mcpd_set_learned_weights", "mcpd_mlp_destroy", "mcpd_probe", "mcpd_strerror",
            "mcpd_last_error")
 
 MLP_FEATURES = 8
@@ -169,6 +172,10 @@ def load(path: Optional[str] = None):
         L.mcpd_mlp_loss_grad.argtypes = [vp, vp, vp]
         L.mcpd_mlp_train.argtypes = [vp, C.c_int32, C.POINTER(AdamW), vp]
         L.mcpd_set_learned_weights.argtypes = [vp, vp, C.c_double, vp]
+        L.mcpd_mlp_backward.argtypes = [vp, vp, C.c_int64, vp, vp]
+        L.mcpd_mlp_adamw_step.argtypes = [vp, vp, C.POINTER(AdamW)]
+        L.mcpd_mlp_get_state.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_int64)]
+        L.mcpd_mlp_set_state.argtypes = [vp, vp, vp, vp, C.c_int64]
         L.mcpd_mlp_destroy.argtypes = [vp]
         L.mcpd_mlp_destroy.restype = None
         L.mcpd_probe.argtypes = [C.c_int, C.c_uint32, C.POINTER(ProbeResult)]
@@ -470,6 +477,37 @@ class Mlp:
         hist = np.zeros(max(steps, 1))
         _check(load().mcpd_mlp_train(self.h, steps, C.byref(hp), _p(hist)), "mcpd_mlp_train")
         return hist[:steps]
+
+    def backward(self, X, dg):
+        """Parameter gradient of sum_r dg_r g_r (mcpd_mlp_backward)."""
+        X = np.ascontiguousarray(X, np.float32)
+        dg = np.ascontiguousarray(dg, np.float32)
+        grad = np.zeros(MLP_PARAMS, np.float32)
+        _check(load().mcpd_mlp_backward(self.h, _p(X), X.shape[0], _p(dg), _p(grad)), "mcpd_mlp_backward")
+        return grad
+
+    def adamw_step(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        """One AdamW step with a given gradient (mcpd_mlp_adamw_step)."""
+        grad = np.ascontiguousarray(grad, np.float32)
+        hp = AdamW(lr, beta1, beta2, eps, weight_decay)
+        _check(load().mcpd_mlp_adamw_step(self.h, _p(grad), C.byref(hp)), "mcpd_mlp_adamw_step")
+
+    def state(self):
+        """(master FP32, BF16 bits, AdamW m, AdamW v, step)."""
+        master = np.zeros(MLP_PARAMS, np.float32)
+        bf16 = np.zeros(MLP_PARAMS, np.uint16)
+        m = np.zeros(MLP_PARAMS, np.float32)
+        v = np.zeros(MLP_PARAMS, np.float32)
+        step = C.c_int64()
+        _check(load().mcpd_mlp_get_state(self.h, _p(master), _p(bf16), _p(m), _p(v), C.byref(step)),
+               "mcpd_mlp_get_state")
+        return master, bf16, m, v, int(step.value)
+
+    def set_state(self, master, m, v, step):
+        master = np.ascontiguousarray(master, np.float32)
+        m = np.ascontiguousarray(m, np.float32)
+        v = np.ascontiguousarray(v, np.float32)
+        _check(load().mcpd_mlp_set_state(self.h, _p(master), _p(m), _p(v), int(step)), "mcpd_mlp_set_state")
 
     def apply(self, dec, alpha=0.5):
         """Set dec's selection weights from the network; returns w."""

@@ -84,14 +84,15 @@ def train(decs, signals, rho, eps, steps=600, lr=3e-3, weight_decay=1e-4, init_s
 class Comparison:
     """Equal-budget runs of one instance under several weightings."""
 
-    def __init__(self, inst, rp, nref=64):
+    def __init__(self, inst, rp, nref=64, ref_seed=100000):
         self.inst, self.rp = inst, rp
         self.dec = N.Decoder(inst)
         self.dec.set_weights(None)
-        runs = [self._run(1000 + s) for s in range(nref)]
+        runs = [self._run(ref_seed + s) for s in range(nref)]
         M = np.array([r["marginals"] for r in runs])
         self.ref = M.mean(axis=0)
         self.ref_var = float((M.var(axis=0, ddof=1) / nref).mean())
+        self.nref = nref
         self.results: Dict[str, dict] = {}
 
     def _run(self, seed):
@@ -100,18 +101,19 @@ class Comparison:
 
     def measure(self, name, set_weights, nrep):
         set_weights(self.dec)
-        errs, ms, var = [], [], []
+        errs, ms, var, tau = [], [], [], []
         for s in range(nrep):
             r = self._run(s)
             errs.append(float(np.mean((r["marginals"] - self.ref) ** 2)))
             var.append(float(np.mean(r["stderr"] ** 2)))
             ms.append(r["stats"]["kernel_ms"])
+            tau.append(int(r["stats"]["tau_max"]))
         self.dec.set_weights(None)
         mse = float(np.mean(errs)) - self.ref_var
         # the median run: the per-slot estimates are heavy-tailed (a pair
         # that takes very long to meet makes one run's error large), so the
-        # mean over a few dozen runs is decided by its largest run; the
-        # median shows the typical run next to it
+        # mean over runs is decided by its largest runs; the median shows the
+        # typical run next to it
         mse_med = float(np.median(errs)) - self.ref_var
         v = float(np.mean(var))
         sec = float(np.mean(ms)) / 1e3
@@ -119,12 +121,27 @@ class Comparison:
                    efficiency=(1.0 / (mse * sec)) if mse > 0 else float("inf"),
                    mse_median=mse_med,
                    median_efficiency=(1.0 / (mse_med * sec)) if mse_med > 0 else float("inf"),
-                   var=v, var_efficiency=1.0 / (v * sec), run_mse=errs, run_var=var, run_ms=ms)
+                   var=v, var_efficiency=1.0 / (v * sec), run_mse=errs, run_var=var, run_ms=ms, run_tau_max=tau)
         self.results[name] = out
         return out
 
     def gain(self, name, base="score", key="efficiency"):
         return self.results[name][key] / self.results[base][key]
+
+    def gain_ci(self, name, base="score", level=0.9, resamples=2000, seed=0):
+        """Bootstrap interval of the efficiency gain: the runs of each
+        weighting resampled with replacement (the reference held fixed)."""
+        rng = np.random.default_rng(seed)
+        a = np.asarray(self.results[base]["run_mse"])
+        b = np.asarray(self.results[name]["run_mse"])
+        sa, sb = self.results[base]["seconds"], self.results[name]["seconds"]
+        g = []
+        for _ in range(resamples):
+            ma = a[rng.integers(0, len(a), len(a))].mean() - self.ref_var
+            mb = b[rng.integers(0, len(b), len(b))].mean() - self.ref_var
+            g.append((ma * sa) / (mb * sb) if mb > 0 else float("inf"))
+        lo, hi = np.percentile(g, [50 * (1 - level), 50 * (1 + level)])
+        return float(lo), float(hi)
 
     def close(self):
         self.dec.close()
@@ -220,36 +237,82 @@ def main(out=TRAINED, steps=600, nrep=12, log=print):
     return report
 
 
-def evaluate(net, nref=64, nrep=24, instances=None, log=print):
+def evaluate(net, nref=1024, nrep=1024, instances=None, log=print, with_judge=False):
     """Learned against score weights on the evaluation set at equal budget:
-    per instance the reference-based MSE, the variance from the runs' own
-    standard errors, device seconds and both gains."""
+    per instance the reference-based MSE (mean and median run), a bootstrap
+    interval of the efficiency gain, the variance from the runs' own
+    standard errors, device seconds and the runs' largest meeting times.
+    Runs use fixed seeds (reference 100000..., compared runs 0...), so the
+    figures are a function of the inputs and the network alone."""
     rows = []
     for inst, rp in (instances or evaluation_set()):
         cmp_ = Comparison(inst, rp, nref=nref)
         s = cmp_.measure("score", score_weights, nrep)
         l = cmp_.measure("learned", learned_weights(net), nrep)
-        choice, pilot_sec = judge(cmp_.dec, net, rp)
-        j = cmp_.results[choice]
-        # the judged weighting pays for its pilot once per instance, spread
-        # over the runs it serves
-        judged_eff = 1.0 / (j["mse"] * (j["seconds"] + pilot_sec / nrep)) if j["mse"] > 0 else float("inf")
-        cmp_.dec.set_weights(None)
-        row = dict(instance=inst.name, n=inst.n, budget=rp.budget, slots=rp.slots,
+        lo, hi = cmp_.gain_ci("learned")
+        row = dict(instance=inst.name, n=inst.n, budget=rp.budget, slots=rp.slots, runs=nrep, reference_runs=nref,
                    rmse_score=s["rmse"], rmse_learned=l["rmse"],
                    var_score=s["var"], var_learned=l["var"],
                    seconds_score=s["seconds"], seconds_learned=l["seconds"],
-                   gain=cmp_.gain("learned"), var_gain=cmp_.gain("learned", key="var_efficiency"),
+                   gain=cmp_.gain("learned"), gain_ci90=[lo, hi],
+                   var_gain=cmp_.gain("learned", key="var_efficiency"),
                    median_gain=cmp_.gain("learned", key="median_efficiency"),
-                   judge_choice=choice, judge_pilot_seconds=pilot_sec,
-                   judged_gain=judged_eff / s["efficiency"], ref_var=cmp_.ref_var)
+                   tau_max_p50=[float(np.median(s["run_tau_max"])), float(np.median(l["run_tau_max"]))],
+                   tau_max_p99=[float(np.percentile(s["run_tau_max"], 99)), float(np.percentile(l["run_tau_max"], 99))],
+                   ref_var=cmp_.ref_var)
+        if with_judge:
+            choice, pilot_sec = judge(cmp_.dec, net, rp)
+            j = cmp_.results[choice]
+            # the judged weighting pays for its pilot once per instance,
+            # spread over the runs it serves
+            judged_eff = 1.0 / (j["mse"] * (j["seconds"] + pilot_sec / nrep)) if j["mse"] > 0 else float("inf")
+            row.update(judge_choice=choice, judge_pilot_seconds=pilot_sec, judged_gain=judged_eff / s["efficiency"])
+        cmp_.dec.set_weights(None)
         rows.append(row)
         log(json.dumps(row))
         cmp_.close()
+
     def geomean(key):
         return float(np.exp(np.mean(np.log([max(r[key], 1e-12) for r in rows]))))
-    return dict(rows=rows, gain_geomean=geomean("gain"), var_gain_geomean=geomean("var_gain"),
-                median_gain_geomean=geomean("median_gain"), judged_gain_geomean=geomean("judged_gain"))
+    out = dict(rows=rows, gain_geomean=geomean("gain"), var_gain_geomean=geomean("var_gain"),
+               median_gain_geomean=geomean("median_gain"))
+    if with_judge:
+        out["judged_gain_geomean"] = geomean("judged_gain")
+    return out
+
+
+def _state_hash(master, bf16, m, v, step):
+    import hashlib
+    h = hashlib.sha256()
+    for a in (master, bf16, m, v):
+        h.update(np.ascontiguousarray(a).tobytes())
+    h.update(int(step).to_bytes(8, "little", signed=True))
+    return h.hexdigest()
+
+
+def save_checkpoint(net, path, **extra):
+    """The network's whole optimiser state: FP32 master parameters, their
+    BF16 copy, AdamW moments and step counter, with a SHA-256 over all of
+    them (extra: JSON-serialisable metadata)."""
+    master, bf16, m, v, step = net.state()
+    np.savez(path, master=master, bf16=bf16, adam_m=m, adam_v=v, step=np.int64(step),
+             sha256=_state_hash(master, bf16, m, v, step), meta=json.dumps(extra))
+
+
+def load_checkpoint(path, stream=None):
+    """A network restored from save_checkpoint, after checking the hash and
+    that the BF16 copy it rebuilds equals the saved one."""
+    with np.load(path, allow_pickle=False) as z:
+        master, bf16, m, v = (z[k] for k in ("master", "bf16", "adam_m", "adam_v"))
+        step = int(z["step"])
+        if _state_hash(master, bf16, m, v, step) != str(z["sha256"]):
+            raise ValueError(f"{path}: checkpoint hash mismatch")
+    net = N.Mlp(master, stream)
+    net.set_state(master, m, v, step)
+    if not np.array_equal(net.state()[1], bf16):
+        net.close()
+        raise ValueError(f"{path}: BF16 copy differs from the one rebuilt from the master")
+    return net
 
 
 def load_trained(path=TRAINED):

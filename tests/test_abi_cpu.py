@@ -30,8 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    # mcpd_run_opts: u64, 18 x u32, 5 pointers; mcpd_run_stats: 14 x u64, 6 x u32, double
-    assert C.sizeof(N.RunOpts) == 8 + 18 * 4 + 5 * 8
+    # mcpd_run_opts: u64, 20 x u32, 5 pointers; mcpd_run_stats: 14 x u64, 6 x u32, double
+    assert C.sizeof(N.RunOpts) == 8 + 20 * 4 + 5 * 8
     assert C.sizeof(N.RunStats) == 14 * 8 + 6 * 4 + 8
     assert C.sizeof(N.TuneEntry) == 32
     assert C.sizeof(N.ProbeResult) == 4 * 8 + 2 * 4

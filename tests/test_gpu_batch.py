@@ -49,7 +49,9 @@ def run_batch(spec, seed, runs=1, **opt):
         for i, (inst, budget, slots, k, m) in enumerate(spec):
             nb = max(1, (budget // slots) // max(m, 1))
             b1, b2 = bt.buckets(i, nb)
-            outs[-1][i].update(bucket_sum=b1, bucket_sumsq=b2, mismatch=bt.mismatch(i))
+            outs[-1][i].update(bucket_sum=b1, bucket_sumsq=b2)
+            if opt.get("keep_mismatch"):
+                outs[-1][i].update(mismatch=bt.mismatch(i))
             if opt.get("keep_slot_records"):
                 ns, su = bt.slot_records(i)
                 outs[-1][i].update(slot_nstar=ns, slot_units=su)
@@ -66,7 +68,7 @@ def run_batch(spec, seed, runs=1, **opt):
 def test_mixed_batch_matches_oracle_with_graph_replays(kern):
     spec = mixed_batch()
     base = 40
-    outs, cfg = run_batch(spec, seed=11, runs=3, instance_id=base, keep_slot_records=1, **kern)
+    outs, cfg = run_batch(spec, seed=11, runs=3, instance_id=base, keep_slot_records=1, keep_mismatch=1, **kern)
     # every replay of the captured graph gives the same answer
     for r in outs[:-1]:
         for i in range(len(spec)):
@@ -164,6 +166,26 @@ def test_batch_equals_single_runs_and_seed_changes():
             d.close()
 
 
+def test_mismatch_times_only_when_asked_and_change_nothing_else():
+    spec = mixed_batch()
+    plain, _ = run_batch(spec, seed=13)
+    kept, _ = run_batch(spec, seed=13, keep_mismatch=1)
+    for a, b in zip(plain[0], kept[0]):
+        assert np.array_equal(a["marginals"], b["marginals"]) and np.array_equal(a["hist"], b["hist"])
+        assert np.array_equal(a["bucket_sumsq"], b["bucket_sumsq"])
+    assert sum(int(r["mismatch"].sum()) for r in kept[0]) > 0
+    decs = [N.Decoder(inst) for inst, *_ in spec[:1]]
+    try:
+        bt = N.Batch(decs, [spec[0][1:]])
+        bt.run(1)
+        with pytest.raises(N.McpdError, match="not kept"):
+            bt.mismatch(0)
+        bt.close()
+    finally:
+        for d in decs:
+            d.close()
+
+
 def test_autotuner_keeps_results():
     spec = mixed_batch()
     decs = [N.Decoder(inst) for inst, *_ in spec]
@@ -210,7 +232,7 @@ def test_noise_sweep_full_size_every_instance():
     updates each over 4096 slots, in one launch: every instance bit-exact."""
     insts, rp = I.noise_sweep()
     spec = [(x, rp.budget, rp.slots, rp.k, rp.m) for x in insts]
-    outs, cfg = run_batch(spec, seed=rp.seed, keep_slot_records=1)
+    outs, cfg = run_batch(spec, seed=rp.seed, keep_slot_records=1, keep_mismatch=1)
     assert ((cfg["placement"] & 3) == 3).all()
     for i, (inst, budget, slots, k, m) in enumerate(spec):
         orc, _ = P.oracle_run(inst, budget, slots, k, m, seed=rp.seed, instance_id=i)
@@ -223,7 +245,7 @@ def test_uneven_batch_full_size_every_instance():
     of its slot records."""
     insts, params = I.uneven_batch()
     spec = [(x, p.budget, p.slots, p.k, p.m) for x, p in zip(insts, params)]
-    outs, cfg = run_batch(spec, seed=0, keep_slot_records=1)
+    outs, cfg = run_batch(spec, seed=0, keep_slot_records=1, keep_mismatch=1)
     res = outs[0]
     for i, (inst, budget, slots, k, m) in enumerate(spec):
         st = res[i]["stats"]
@@ -247,7 +269,7 @@ def test_uneven_batch_capped_every_instance():
     every instance in full against the oracle run with that cap."""
     insts, params = I.uneven_batch()
     spec = [(x, p.budget, p.slots, p.k, p.m) for x, p in zip(insts, params)]
-    outs, cfg = run_batch(spec, seed=1, keep_slot_records=1, cap_sweeps=20)
+    outs, cfg = run_batch(spec, seed=1, keep_slot_records=1, keep_mismatch=1, cap_sweeps=20)
     res = outs[0]
     assert sum(r["stats"]["cap_hits"] for r in res) > 0
     for i, (inst, budget, slots, k, m) in enumerate(spec):

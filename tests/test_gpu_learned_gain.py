@@ -1,39 +1,49 @@
 """What the trained selection network gains over the paper's score weights
-at equal budget, with the score weights as judge (paper_2608_30239_amd/
-selection.py has the protocol).  Equal budget means equal progress units
-and slots; the gain is the ratio of 1 / (MSE x device seconds), MSE against
-an independent long reference run with its own variance removed.
+at equal budget (paper_2608_30239_amd/selection.py has the protocol), on the
+five held-out evaluation instances: the paper-shaped 1298 x 97 instance and
+four 20000-clone instances (the network saw only the uneven batch).  Equal
+budget means equal progress units and slots; the gain is the ratio of
+1 / (MSE x device seconds), MSE against the mean of 1024 independent
+reference runs with its own variance removed, over 1024 runs per weighting.
 
-Measured on the paper-shaped instance (1298 clones, 97 pools, budget 2^28,
-65536 slots), held out from training (the network saw only the uneven batch
-of 256 instances).  Runs take about 12 ms each."""
+Every run has a fixed seed, so every figure here is a function of the
+inputs and the shipped network alone.  On the 20000-clone instances the
+run-level error is heavy-tailed (the mean over runs is set by the few runs
+that drew a pair taking very long to meet), so each gain comes with a 90%
+bootstrap interval and the median run's gain beside it."""
 
 import numpy as np
 import pytest
-
-from paper_2608_30239_amd import instances as I
 
 pytestmark = pytest.mark.gpu
 
 N = pytest.importorskip("paper_2608_30239_amd.native")
 S = pytest.importorskip("paper_2608_30239_amd.selection")
+from paper_2608_30239_amd import instances as I  # noqa: E402
 
 
-def test_trained_network_beats_score_weights_on_paper_shaped_instance():
+def test_trained_network_against_score_weights_on_the_evaluation_set():
     params, report = S.load_trained()
     assert params.shape == (N.MLP_PARAMS,) and np.isfinite(params).all()
     net = N.Mlp(params)
     try:
-        res = S.evaluate(net, nref=48, nrep=24, instances=[I.paper_shaped()], log=print)
+        res = S.evaluate(net, nref=1024, nrep=1024, log=lambda m: print(m, flush=True))
     finally:
         net.close()
-    row = res["rows"][0]
-    print(f"gain {row['gain']:.2f} (variance-based {row['var_gain']:.2f}), judge chose {row['judge_choice']}, "
-          f"judged gain {row['judged_gain']:.2f}")
-    # both measures of the same quantity agree on the direction and the size
-    assert row["gain"] > 1.3 and row["var_gain"] > 1.3
-    assert row["judge_choice"] == "learned" and row["judged_gain"] > 1.2
-    assert row["rmse_learned"] < row["rmse_score"]
+    rows = {r["instance"]: r for r in res["rows"]}
+    for name, r in rows.items():
+        print(f"{name}: gain {r['gain']:.2f} (90% CI {r['gain_ci90'][0]:.2f}-{r['gain_ci90'][1]:.2f}), "
+              f"median run {r['median_gain']:.2f}, runs {r['runs']}", flush=True)
+        assert np.isfinite(r["gain"]) and r["gain"] > 0
+        lo, hi = r["gain_ci90"]
+        assert lo <= r["gain"] <= hi
+        # the typical run is not made worse anywhere
+        assert r["median_gain"] > 0.8
+    print(f"geometric mean gain {res['gain_geomean']:.2f}", flush=True)
+    # the paper-shaped instance: a clear win, its whole interval above one
+    k = rows["knill1298x97"]
+    assert k["gain"] > 1.3 and k["gain_ci90"][0] > 1.0
+    assert res["gain_geomean"] > 1.0
 
 
 def test_zero_residual_network_is_the_score_weights():
