@@ -96,6 +96,7 @@ struct InstDesc {
     uint32_t place;         // Place bits
     uint32_t lds_hist, lds_tab;
     uint32_t lds_state, wave_words;   // cooperative kernel: first group's state, words per group
+    uint32_t lds_stats;     // cooperative kernel: the groups' statistics (ST_COUNT words of 64 bits each)
     uint32_t tab_off_thr, tab_off_alias, tab_off_rows, tab_bytes;   // within the table block (bytes)
     // Outputs (zeroed before the launch).
     int64_t *S1;            // [nbuckets * n]

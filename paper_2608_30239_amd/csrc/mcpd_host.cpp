@@ -305,6 +305,7 @@ struct Config {
 struct Layout {
     uint32_t words_bits, words_cnt, lanes, place, lds_hist, lds_tab, lds_state, wave_words;
     uint32_t off_thr, off_alias, off_rows, tab_bytes;
+    uint32_t lds_stats = 0;   // cooperative layout: the groups' statistics
     size_t used;
 };
 
@@ -368,8 +369,9 @@ int layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, u
     return MCPD_OK;
 }
 
-// Placement for the cooperative kernel: the histogram, the tables when they
-// fit, and one chain state per group of lanes (words rounded to 16 bytes).
+// Placement for the cooperative kernel: the histogram, the groups'
+// statistics, the tables when they fit, and one chain state per group of
+// lanes (words rounded to 16 bytes).
 // Returns false when the groups' states do not fit.
 bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan,
                  uint32_t group_log2, Layout &L)
@@ -389,11 +391,17 @@ bool coop_layout(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t bud
     // the thresholds alone, when the other tables stay in global memory
     const size_t thr = align16((size_t)I->thr_len * 8u);
     const bool thr_lds = !tl && plan == 0 && fmt_entries(fmt) <= 8 && pat + hist + thr + states <= budget;
+    const size_t tabs = tl ? L.tab_bytes : thr_lds ? thr : 0;
+    // the groups' statistics, in LDS when they fit beside everything else
+    // (they never displace the tables), else in global memory
+    const size_t stats = align16(groups * ST_COUNT * 8u);
+    const bool stats_lds = pat + hist + stats + tabs + states <= budget;
     L.lanes = (uint32_t)groups;
     L.place = PLACE_STATE_LDS | PLACE_COOP | (tl ? PLACE_TABLES_LDS : 0u) | (thr_lds ? PLACE_THR_LDS : 0u);
     L.lds_hist = (uint32_t)(pat / 4);
-    L.lds_tab = (uint32_t)((pat + hist) / 4);
-    L.lds_state = L.lds_tab + (tl ? L.tab_bytes / 4 : thr_lds ? (uint32_t)(thr / 4) : 0u);
+    L.lds_stats = stats_lds ? (uint32_t)((pat + hist) / 4) : 0u;   // 0 = in global memory
+    L.lds_tab = (uint32_t)((pat + hist + (stats_lds ? stats : 0)) / 4);
+    L.lds_state = L.lds_tab + (uint32_t)(tabs / 4);
     L.wave_words = (uint32_t)ww;
     L.used = (size_t)L.lds_state * 4 + states;
     return true;
@@ -677,6 +685,7 @@ int plan(Launch &L, const Config &c)
         d.lds_tab = lay.lds_tab;
         d.lds_state = lay.lds_state;
         d.wave_words = lay.wave_words;
+        d.lds_stats = lay.lds_stats;
         d.tab_off_thr = lay.off_thr;
         d.tab_off_alias = lay.off_alias;
         d.tab_off_rows = lay.off_rows;

@@ -824,7 +824,7 @@ __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
 constexpr uint32_t COOP_WAVES = WG / 64;   // wavefronts per workgroup
 
 struct GroupSlot {
-    uint32_t mode, p, r, t, nret, tau, target, lim, stop, lc, f0, f1;
+    uint32_t mode, p, r, t, nret, tau, target, lim, stop, lc, cptr;
     int32_t mu, sgn;
     uint64_t S;
 };
@@ -849,11 +849,18 @@ struct Coop {
     int64_t *acc;           // this group's numerator row
     uint32_t *list;         // its touched list
     uint32_t *hist_lds;
-    uint64_t *ls;           // its statistics (global, written by the leader)
+    uint32_t *lds;          // the workgroup's dynamic LDS
     uint32_t gid;           // the group whose slot this is (index in the workgroup)
+    // The slot's numerator cache: one (clone, numerator) entry per lane of
+    // the group, no clone held twice.  The events of a slot add up here; an
+    // entry moves to the numerator row only when a new clone needs its lane
+    // (lanes taken in turn), so most slots never touch the row.  Entries
+    // are empty (NO_TAG) between slots, which a merged group relies on.
+    mutable uint32_t ckey;
+    mutable uint64_t cval;
 
-    // Point at the state, numerator row, touched list and statistics of
-    // group `g` of this workgroup.
+    // Point at the state, numerator row and touched list of group `g` of
+    // this workgroup (its statistics follow from gid).
     __device__ __forceinline__ void point(uint32_t *smem, uint32_t g)
     {
         gid = g;
@@ -862,7 +869,34 @@ struct Coop {
         const size_t gi = (size_t)blockIdx.x * (COOP_WAVES * (64u >> a.group_log2)) + g;
         acc = a.acc + gi * (size_t)a.acc_stride;
         list = a.lists + gi * (size_t)a.list_cap;
-        ls = a.lane_stats + gi * ST_COUNT;
+    }
+
+    // The group's statistics, written by its leader: in LDS when the layout
+    // has room for them (lds_stats != 0), else in global memory.  Both
+    // pointers keep their address spaces, so neither access becomes a flat
+    // one, and both are formed where they are used (no live registers).
+    __device__ __forceinline__ __attribute__((address_space(3))) uint64_t *stats_lds() const
+    {
+        return (__attribute__((address_space(3))) uint64_t *)(reinterpret_cast<uint64_t *>(lds + D->lds_stats) +
+                                                              (size_t)gid * ST_COUNT);
+    }
+    __device__ __forceinline__ __attribute__((address_space(1))) uint64_t *stats_global() const
+    {
+        const size_t gi = (size_t)blockIdx.x * (COOP_WAVES * (64u >> a.group_log2)) + gid;
+        return (__attribute__((address_space(1))) uint64_t *)(a.lane_stats + gi * ST_COUNT);
+    }
+
+    // Counter i of the group's statistics (LDS or global; the choice is the
+    // instance's, so the branch is uniform).
+    __device__ __forceinline__ uint64_t stat_get(uint32_t i) const
+    {
+        return D->lds_stats ? __hip_atomic_load(stats_lds() + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)
+                            : __hip_atomic_load(stats_global() + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __device__ __forceinline__ void stat_clear(uint32_t i) const
+    {
+        if (D->lds_stats) stats_lds()[i] = 0;
+        else stats_global()[i] = 0;
     }
 
     // The group's statistics into the instance's, once, when it runs out of
@@ -871,7 +905,7 @@ struct Coop {
     {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) {
-            const uint64_t v = __hip_atomic_load(ls + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint64_t v = stat_get(i);
             if (v) {
                 if (i == ST_TAU_MAX || i == ST_NSTAR_MAX)
                     atomicMax(reinterpret_cast<unsigned long long *>(D->stats + i), (unsigned long long)v);
@@ -883,11 +917,15 @@ struct Coop {
 
     __device__ __forceinline__ void stat_add(int i, uint64_t v) const
     {
-        if (gl == 0) __hip_atomic_fetch_add(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (gl != 0) return;
+        if (D->lds_stats) __hip_atomic_fetch_add(stats_lds() + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else __hip_atomic_fetch_add(stats_global() + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __device__ __forceinline__ void stat_max(int i, uint64_t v) const
     {
-        if (gl == 0) __hip_atomic_fetch_max(ls + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (gl != 0) return;
+        if (D->lds_stats) __hip_atomic_fetch_max(stats_lds() + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else __hip_atomic_fetch_max(stats_global() + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
     __device__ __forceinline__ uint32_t site(uint32_t sw) const
@@ -1012,6 +1050,30 @@ struct Coop {
         lds_fence();
     }
 
+    // Event v (signed) of clone j, told to every lane of the group: added to
+    // the lane that holds j, else to the lane whose turn it is, whose old
+    // entry (if it holds anything) goes to the row and the touched list.
+    __device__ __forceinline__ void record(uint32_t j, uint64_t v, GroupSlot &s) const
+    {
+        if ((__ballot(ckey == j) & gmask) != 0) {
+            if (ckey == j) cval += v;
+            return;
+        }
+        const bool mine = gl == s.cptr;
+        s.cptr = (s.cptr + 1u) & (gsz - 1u);
+        const bool out = mine && ckey != NO_TAG && cval != 0;
+        if (out) {
+            add(ckey, cval);
+            if (s.lc < a.list_cap)
+                __hip_atomic_store(list + s.lc, ckey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if ((__ballot(out) & gmask) != 0) s.lc += 1u;
+        if (mine) {
+            ckey = j;
+            cval = v;
+        }
+    }
+
     __device__ __forceinline__ void emit(uint32_t nstar, uint32_t j, int64_t v) const
     {
         if (nstar > D->nbuckets) {
@@ -1054,6 +1116,24 @@ struct Coop {
     __device__ void flush_slot(GroupSlot &s) const
     {
         const uint32_t nstar = s.nret;
+        const bool held = ckey != NO_TAG && cval != 0;
+        if (s.lc == 0u) {
+            // nothing went to the row: the cache holds the slot's numerators
+            if (held) emit(nstar, ckey, (int64_t)cval);
+            ckey = NO_TAG;
+            cval = 0;
+            finish_slot(s, nstar);
+            return;
+        }
+        // the row holds part of them: the entries join it, then the row is flushed
+        if (held) add(ckey, cval);
+        const uint64_t hm = (__ballot(held) & gmask) >> leader;
+        const uint32_t at = s.lc + (uint32_t)__builtin_popcountll(hm & ((1ull << gl) - 1ull));
+        if (held && at < a.list_cap)
+            __hip_atomic_store(list + at, ckey, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        s.lc += (uint32_t)__builtin_popcountll(hm);
+        ckey = NO_TAG;
+        cval = 0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         if (s.lc <= a.list_cap) {
             for (uint32_t e = gl; e < s.lc; e += gsz) {
@@ -1070,6 +1150,11 @@ struct Coop {
                 if (v != 0) emit(nstar, j, v);
             }
         }
+        finish_slot(s, nstar);
+    }
+
+    __device__ __forceinline__ void finish_slot(GroupSlot &s, uint32_t nstar) const
+    {
         if (gl == 0) {
             if (D->slot_nstar) D->slot_nstar[s.p - D->p0] = nstar;
             if (D->slot_units) D->slot_units[s.p - D->p0] = s.S;
@@ -1240,6 +1325,7 @@ struct Coop {
         // the first changing lane applies its update and its estimator
         // events, then tells the group (mu change + 1, event flag, site)
         uint32_t msg = 0;
+        uint64_t ev_val = 0;   // the event's signed value (changing lane)
         if (gl == f) {
             const int dx = (int)xn - (int)xi;
             const int dy = (int)yn - (int)yi;
@@ -1263,19 +1349,17 @@ struct Coop {
                 val -= (uint64_t)(int64_t)(dx - dy) * gsum(t, D->k, D->ell, D->W);
             uint32_t ev = 0;
             if (val != 0) {
-                add(I, s.sgn > 0 ? val : (uint64_t)0 - val);
+                ev_val = s.sgn > 0 ? val : (uint64_t)0 - val;
                 ev = 1;
             }
             msg = (uint32_t)(dmu + 1) | (ev << 2) | (I << 3);
         }
-        msg = __shfl(msg, (int)(leader + f));
-        const uint32_t If = msg >> 3;
-        if ((msg & 4u) && If != s.f0 && If != s.f1) {
-            if (gl == 0 && s.lc < a.list_cap)
-                __hip_atomic_store(list + s.lc, If, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            s.lc += 1u;
-            s.f1 = s.f0;
-            s.f0 = If;
+        const int src = (int)(leader + f);
+        msg = __shfl(msg, src);
+        if (msg & 4u) {
+            const uint64_t v = ((uint64_t)(uint32_t)__shfl((uint32_t)(ev_val >> 32), src) << 32) |
+                               (uint64_t)(uint32_t)__shfl((uint32_t)ev_val, src);
+            record(msg >> 3, v, s);
         }
         if (s.tau == 0u) {
             s.mu += (int)(msg & 3u) - 1;
@@ -1327,17 +1411,18 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                   nullptr,
                   nullptr,
                   hist_lds,
-                  nullptr,
-                  0u};
+                  smem,
+                  0u,
+                  NO_TAG,
+                  0ull};
     C.point(smem, wave * groups + g);
-    for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) C.ls[i] = 0;
+    for (uint32_t i = gl; i < (uint32_t)ST_COUNT; i += gsz) C.stat_clear(i);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __syncthreads();
     const uint32_t P = D->P;
     GroupSlot s;
     s.mode = MODE_NEED_SLOT;
-    s.p = s.r = s.t = s.nret = s.tau = s.target = s.lim = s.stop = s.lc = 0;
-    s.f0 = s.f1 = NO_TAG;
+    s.p = s.r = s.t = s.nret = s.tau = s.target = s.lim = s.stop = s.lc = s.cptr = 0;
     s.mu = 0;
     s.sgn = 1;
     s.S = 0;
@@ -1358,7 +1443,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                     s.S = 0;
                     s.nret = 0;
                     s.lc = 0;
-                    s.f0 = s.f1 = NO_TAG;
+                    s.cptr = 0;
                     s.sgn = 1;
                     s.mode = MODE_NEED_REP;
                 }
@@ -1391,8 +1476,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
                 t.lim = __shfl(s.lim, src);
                 t.stop = __shfl(s.stop, src);
                 t.lc = __shfl(s.lc, src);
-                t.f0 = __shfl(s.f0, src);
-                t.f1 = __shfl(s.f1, src);
+                t.cptr = __shfl(s.cptr, src);
                 t.mu = __shfl(s.mu, src);
                 t.sgn = __shfl(s.sgn, src);
                 t.S = ((uint64_t)__shfl((uint32_t)(s.S >> 32), src) << 32) | (uint64_t)__shfl((uint32_t)s.S, src);
