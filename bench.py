@@ -182,7 +182,9 @@ def batch_lines(steps: int):
             cfg = bt.config()
             out[name] = dict(instances=len(insts), graph_ms=sum(ms) / len(ms),
                              updates_per_s=units / (sum(ms) / 1e3), kernel=r[0]["stats"]["kernel"],
-                             group_lanes=r[0]["stats"]["group_lanes"], wg_per_cu=cfg["wg_per_cu"],
+                             group_lanes={str(g): sum(x["stats"]["group_lanes"] == g for x in r)
+                                          for g in sorted({x["stats"]["group_lanes"] for x in r})},
+                             wg_per_cu=cfg["wg_per_cu"],
                              ticket_slots=cfg["ticket_slots"], tuner_candidates=len(tuned),
                              tau_max=max(x["stats"]["tau_max"] for x in r),
                              cap_hits=sum(x["stats"]["cap_hits"] for x in r))

@@ -90,7 +90,10 @@ typedef struct mcpd_run_opts {
                                lanes, one speculative draw per lane and step),
                                MCPD_EINVAL if the states do not fit           */
     uint32_t group_lanes;   /* cooperative kernel: lanes per slot, 8, 16, 32 or
-                               64 (0 = default 16)                            */
+                               64 for every instance; 0 = each instance its
+                               own: the least of 16, 32 and 64 whose layout
+                               keeps the instance's tables in LDS, else the
+                               least whose chain states fit               */
     uint32_t init_mode;     /* initial distribution nu of every pair (Algorithm
                                3: Z_0 ~ nu, X_0 = Y_0 = Z_0): 0 = all-negative
                                state (default); 1 = the prior, clones
@@ -178,7 +181,9 @@ typedef struct mcpd_tune_entry {
     uint32_t narrow_lanes;        /* least lanes of a narrow LDS layout (0 = wide
                                      layouts only)                              */
     uint32_t kernel;              /* 1 = lane kernel, 2 = cooperative kernel    */
-    uint32_t group_lanes;         /* lanes per slot (1 for the lane kernel)     */
+    uint32_t group_lanes;         /* lanes per slot (1 for the lane kernel; 0 =
+                                     chosen per instance, as group_lanes = 0
+                                     of mcpd_run_opts)                          */
     uint32_t reserved;
     double ms;                    /* sampler time of one full run               */
 } mcpd_tune_entry;

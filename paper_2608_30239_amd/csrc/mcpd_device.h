@@ -97,6 +97,7 @@ struct InstDesc {
     uint32_t lds_hist, lds_tab;
     uint32_t lds_state, wave_words;   // cooperative kernel: first group's state, words per group
     uint32_t lds_stats;     // cooperative kernel: the groups' statistics (ST_COUNT words of 64 bits each)
+    uint32_t group_log2;    // cooperative kernel: log2 of the lanes that run one slot of this instance (3..6)
     uint32_t tab_off_thr, tab_off_alias, tab_off_rows, tab_bytes;   // within the table block (bytes)
     // Outputs (zeroed before the launch).
     int64_t *S1;            // [nbuckets * n]
@@ -129,7 +130,8 @@ struct LaunchArgs {
     uint32_t list_cap;          // touched-list capacity per lane
     uint32_t acc_stride;        // >= every n
     uint32_t gwords;            // >= every global-state instance's words_bits + words_cnt
-    uint32_t group_log2;        // cooperative kernel: log2 of the lanes that run one slot (3..6)
+    uint32_t groups_per_wg;     // cooperative kernel: workspace rows (numerator rows, lists,
+                                // statistics) per workgroup, the most groups of any instance
     uint32_t init_mode;         // 0: all-negative initial state; 1: drawn from the prior
     uint32_t mismatch;          // 1: count the mismatch times (Dmis of each instance)
     const uint64_t *seed;       // device copy of the 64-bit key

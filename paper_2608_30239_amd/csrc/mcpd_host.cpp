@@ -297,7 +297,8 @@ struct Config {
     uint32_t spl = 1;         // slots per lane (or per group) one ticket stands for
     uint32_t narrow = 8;      // least lanes of a narrow LDS layout (0 = none)
     bool coop = false;        // the cooperative kernel (one slot per group of lanes)
-    uint32_t group_log2 = 4;  // its lanes per slot: 2^group_log2 (3..6)
+    uint32_t group_log2 = 4;  // its lanes per slot: 2^group_log2 (3..6), or the least of them ...
+    bool mixed = false;       // ... when each instance takes its own (pick_group)
 };
 
 
@@ -429,6 +430,7 @@ struct Launch {
     int grid = 0;
     size_t lds = 0;
     uint32_t acc_stride = 1, gwords = 0, list_cap = 64;
+    uint32_t groups_per_wg = 0;   // cooperative kernel: workspace rows per workgroup (most groups of any instance)
     std::vector<InstDesc> desc;
     std::vector<uint32_t> tickets;
     std::vector<size_t> off;       // word offset of each item's output block
@@ -546,16 +548,52 @@ uint32_t narrow_of(const mcpd_run_opts &o)
     return o.narrow_lanes >= WG_LANES ? 0u : o.narrow_lanes;
 }
 
+// Group size of one instance when each instance takes its own: the
+// smallest from 2^lg_lo lanes up whose layout keeps the instance's tables in
+// LDS, else the smallest whose chain states fit (fewer lanes per slot drop
+// fewer speculative draws, and tables in LDS beat every group size with
+// tables in global memory).  False when no size fits.
+bool pick_group(const mcpd_instance *I, int fmt, uint32_t hist_bins, size_t budget, uint32_t plan, uint32_t lg_lo,
+                Layout &L, uint32_t &lg_out)
+{
+    bool found = false;
+    for (uint32_t lg = lg_lo; lg <= 6; ++lg) {
+        Layout t;
+        if (!coop_layout(I, fmt, hist_bins, budget, plan, lg, t)) continue;
+        if (t.place & PLACE_TABLES_LDS) {
+            L = t;
+            lg_out = lg;
+            return true;
+        }
+        if (!found) {
+            L = t;
+            lg_out = lg;
+            found = true;
+        }
+    }
+    return found;
+}
+
+// Layout and group size of an instance under (lg, mixed).
+bool coop_place(const Launch &L, const mcpd_instance *I, size_t budget, uint32_t lg, bool mixed, Layout &lay,
+                uint32_t &lg_out)
+{
+    if (mixed) return pick_group(I, L.fmt, L.opts.hist_bins, budget, L.opts.plan, lg, lay, lg_out);
+    lg_out = lg;
+    return coop_layout(I, L.fmt, L.opts.hist_bins, budget, L.opts.plan, lg, lay);
+}
+
 // Workgroups per CU at which every instance fits the cooperative layout
 // (0 if none).
-uint32_t coop_wg(const Launch &L, uint32_t most, uint32_t group_log2)
+uint32_t coop_wg(const Launch &L, uint32_t most, uint32_t group_log2, bool mixed)
 {
     for (uint32_t wg = most; wg >= 1; --wg) {
         const size_t budget = wg_lds_budget(wg);
         bool all = true;
         for (const Item &it : L.items) {
             Layout lay;
-            if (!coop_layout(it.I, L.fmt, L.opts.hist_bins, budget, L.opts.plan, group_log2, lay)) {
+            uint32_t lg;
+            if (!coop_place(L, it.I, budget, group_log2, mixed, lay, lg)) {
                 all = false;
                 break;
             }
@@ -568,18 +606,27 @@ uint32_t coop_wg(const Launch &L, uint32_t most, uint32_t group_log2)
 // Workgroups per CU for the cooperative kernel, at most `most`: the issue
 // rate of a CU is shared by its wavefronts, so a launch takes about
 // (rounds of slots) x (wavefronts per SIMD) slot-times, with rounds =
-// ceil(slots / slots running at once).  The count with the fewest is taken,
-// the larger on ties; a fractional last round leaves most groups idle.
-uint32_t coop_wg_for_rounds(const Launch &L, uint32_t most, uint32_t group_log2)
+// ceil(slots / slots running at once) (with group sizes per instance, each
+// instance's slots count in units of the workgroup's groups for it).  The
+// count with the fewest is taken, the larger on ties; a fractional last
+// round leaves most groups idle.
+uint32_t coop_wg_for_rounds(const Launch &L, uint32_t most, uint32_t group_log2, bool mixed)
 {
-    uint64_t slots = 0;
-    for (const Item &it : L.items) slots += it.slots;
-    const uint64_t per_wg = (uint64_t)COOP_WAVES_PER_WG * (64u >> group_log2);
     uint32_t best = most;
     uint64_t best_cost = UINT64_MAX;
     for (uint32_t w = most; w >= 1; --w) {
-        const uint64_t at_once = (uint64_t)L.cus * w * per_wg;
-        const uint64_t cost = ((slots + at_once - 1) / at_once) * w;
+        const size_t budget = wg_lds_budget(w);
+        // workgroup-loads of slots: sum over instances of slots / groups per workgroup
+        uint64_t num = 0;
+        const uint64_t den = (uint64_t)COOP_WAVES_PER_WG * 64u;   // lanes of a workgroup
+        for (const Item &it : L.items) {
+            Layout lay;
+            uint32_t lg = group_log2;
+            if (!coop_place(L, it.I, budget, group_log2, mixed, lay, lg)) lg = group_log2;
+            num += (uint64_t)it.slots << lg;   // slots x lanes per slot
+        }
+        const uint64_t at_once = (uint64_t)L.cus * w * den;
+        const uint64_t cost = ((num + at_once - 1) / at_once) * w;
         if (cost < best_cost) {
             best_cost = cost;
             best = w;
@@ -589,8 +636,9 @@ uint32_t coop_wg_for_rounds(const Launch &L, uint32_t most, uint32_t group_log2)
 }
 
 // The default configuration.  The cooperative kernel when every instance's
-// chain states fit it (workgroups per CU by coop_wg_for_rounds within what
-// LDS and registers allow).  Otherwise the lane kernel: one workgroup per CU
+// chain states fit it (workgroups per CU: for one instance by
+// coop_wg_for_rounds, for a batch the most that LDS and registers allow;
+// group sizes per instance unless the options fix one).  Otherwise the lane kernel: one workgroup per CU
 // when most of the work keeps its chain state in LDS (that already takes the
 // LDS), else as many as the registers allow (more waves hide the latency of
 // global state).
@@ -600,11 +648,18 @@ Config default_config(const Launch &L)
     c.narrow = narrow_of(L.opts);
     const uint32_t kernel = L.opts.kernel;
     const uint32_t lg = group_log2_of(L.opts);
-    uint32_t cw = kernel == 1 ? 0u : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : coop_waves_per_simd(L.fmt), lg);
-    if (cw && !L.opts.wg_per_cu) cw = coop_wg_for_rounds(L, cw, lg);
+    const bool mixed = L.opts.group_lanes == 0;   // each instance its own group size
+    uint32_t cw = kernel == 1 ? 0u
+                              : coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : coop_waves_per_simd(L.fmt), lg, mixed);
+    // the rounds argument holds for one instance, whose slots cost about the
+    // same; a batch's slots do not, its queue balances them, and it runs best
+    // at the most workgroups that fit (measured: the 128-instance noise sweep
+    // 15.2 ms at 5 per CU against 16.9 at the 4 that rounds would pick)
+    if (cw && !L.opts.wg_per_cu && L.items.size() == 1) cw = coop_wg_for_rounds(L, cw, lg, mixed);
     if (cw) {
         c.coop = true;
         c.group_log2 = lg;
+        c.mixed = mixed;
         c.wg_per_cu = cw;
         c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 4u;
         return c;
@@ -640,13 +695,16 @@ int plan(Launch &L, const Config &c)
     L.gwords = 0;
     size_t words = CTRL_WORDS;   // control: error flags and the ticket queues' counters
     size_t slots_total = 0;
+    uint32_t lg_min = 6;
     for (size_t i = 0; i < count; ++i) {
         const Item &it = L.items[i];
         mcpd_instance *I = it.I;
         Layout lay;
+        uint32_t lg = 0;
         if (c.coop) {
-            if (!coop_layout(I, L.fmt, o.hist_bins, budget, o.plan, c.group_log2, lay))
+            if (!coop_place(L, I, budget, c.group_log2, c.mixed, lay, lg))
                 return fail(MCPD_EINVAL, "an instance's chain states do not fit the cooperative layout");
+            lg_min = std::min(lg_min, lg);
         } else {
             int rc = layout(I, L.fmt, o.hist_bins, budget, o.plan, c.narrow, lay);
             if (rc) return rc;
@@ -686,6 +744,7 @@ int plan(Launch &L, const Config &c)
         d.lds_state = lay.lds_state;
         d.wave_words = lay.wave_words;
         d.lds_stats = lay.lds_stats;
+        d.group_log2 = lg;
         d.tab_off_thr = lay.off_thr;
         d.tab_off_alias = lay.off_alias;
         d.tab_off_rows = lay.off_rows;
@@ -753,7 +812,8 @@ int plan(Launch &L, const Config &c)
     L.list_cap = std::min<uint32_t>(4096, std::max<uint32_t>(64, L.acc_stride / 4));
     // numerator rows, touched lists and statistics rows: one per lane of the
     // lane kernel, one per group of the cooperative kernel
-    const size_t rows_per_wg = c.coop ? (size_t)(WG_LANES >> c.group_log2) : (size_t)WG_LANES;
+    const size_t rows_per_wg = c.coop ? (size_t)(WG_LANES >> lg_min) : (size_t)WG_LANES;
+    L.groups_per_wg = c.coop ? (uint32_t)rows_per_wg : 0u;
     int rc;
     if (L.arena) {
         // Carve every buffer from the arena, fixed parts first; the grid
@@ -869,7 +929,7 @@ LaunchArgs launch_args(const Launch &L)
     a.list_cap = L.list_cap;
     a.acc_stride = L.acc_stride;
     a.gwords = L.gwords;
-    a.group_log2 = L.cfg.group_log2;
+    a.groups_per_wg = L.groups_per_wg;
     a.init_mode = L.opts.init_mode;
     a.mismatch = (L.opts.keep_mismatch || L.opts.mismatch) ? 1u : 0u;
     a.seed = L.d_seed;
@@ -1028,7 +1088,7 @@ int finish_item(const Launch &L, size_t i, double *marginals, double *stderr_out
         stats->wg_per_cu = L.cfg.wg_per_cu;
         stats->wg_slots = d.lanes;
         stats->kernel = L.coop ? 2u : 1u;
-        stats->group_lanes = L.coop ? 1u << L.cfg.group_log2 : 1u;
+        stats->group_lanes = L.coop ? 1u << d.group_log2 : 1u;
         stats->kernel_ms = L.last_ms;
     }
     if (L.opts.strict_cap && st[ST_CAP_HITS]) return fail(MCPD_ECAP, "a retained pair hit the meeting cap");
@@ -1480,10 +1540,11 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
         }
     }
     if (L.opts.kernel != 1) {
+        const uint32_t most = L.opts.wg_per_cu ? L.opts.wg_per_cu : mcpd::coop_waves_per_simd(L.fmt);
         const uint32_t lgs[] = {3, 4, 5, 6};
         for (uint32_t lg : lgs) {
             if (L.opts.group_lanes && lg != group_log2_of(L.opts)) continue;
-            const uint32_t top = coop_wg(L, L.opts.wg_per_cu ? L.opts.wg_per_cu : mcpd::coop_waves_per_simd(L.fmt), lg);
+            const uint32_t top = coop_wg(L, most, lg, false);
             if (!top) continue;
             Config c;
             c.coop = true;
@@ -1492,9 +1553,23 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
             c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 4u;
             cands.push_back(c);
             // and the count that leaves no fractional last round of slots
-            const uint32_t w = L.opts.wg_per_cu ? top : coop_wg_for_rounds(L, top, lg);
+            const uint32_t w = L.opts.wg_per_cu ? top : coop_wg_for_rounds(L, top, lg, false);
             if (w != top) {
                 c.wg_per_cu = w;
+                cands.push_back(c);
+            }
+        }
+        // group sizes per instance (from 16 lanes up), at every workgroup count that fits
+        if (!L.opts.group_lanes) {
+            const uint32_t top = coop_wg(L, most, 4, true);
+            for (uint32_t w = top; w >= 1; --w) {
+                if (L.opts.wg_per_cu && w != L.opts.wg_per_cu) continue;
+                Config c;
+                c.coop = true;
+                c.group_log2 = 4;
+                c.mixed = true;
+                c.wg_per_cu = w;
+                c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 4u;
                 cands.push_back(c);
             }
         }
@@ -1513,7 +1588,8 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
         if ((rc = execute(L, seed + 1, false))) return rc;
         ms = 0.5 * (ms + L.last_ms);
         if (entries && done < cap)
-            entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, c.narrow, c.coop ? 2u : 1u, c.coop ? 1u << c.group_log2 : 1u, 0u, ms};
+            entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, c.narrow, c.coop ? 2u : 1u,
+                                            c.coop ? (c.mixed ? 0u : 1u << c.group_log2) : 1u, 0u, ms};
         ++done;
         if (ms < best_ms) { best_ms = ms; best = c; }
     }

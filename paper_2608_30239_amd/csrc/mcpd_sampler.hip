@@ -866,7 +866,7 @@ struct Coop {
         gid = g;
         st = smem + D->lds_state + g * D->wave_words;
         cst = st + D->words_bits;
-        const size_t gi = (size_t)blockIdx.x * (COOP_WAVES * (64u >> a.group_log2)) + g;
+        const size_t gi = (size_t)blockIdx.x * a.groups_per_wg + g;
         acc = a.acc + gi * (size_t)a.acc_stride;
         list = a.lists + gi * (size_t)a.list_cap;
     }
@@ -882,7 +882,7 @@ struct Coop {
     }
     __device__ __forceinline__ __attribute__((address_space(1))) uint64_t *stats_global() const
     {
-        const size_t gi = (size_t)blockIdx.x * (COOP_WAVES * (64u >> a.group_log2)) + gid;
+        const size_t gi = (size_t)blockIdx.x * a.groups_per_wg + gid;
         return (__attribute__((address_space(1))) uint64_t *)(a.lane_stats + gi * ST_COUNT);
     }
 
@@ -1375,7 +1375,7 @@ __device__ __forceinline__ void coop_item(const LaunchArgs &a, DescPtr D, uint32
 {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, wave = tid >> 6;
-    const uint32_t lg = a.group_log2;                 // log2 of the lanes per group
+    const uint32_t lg = D->group_log2;                // log2 of the lanes per group (the instance's)
     const uint32_t gsz = 1u << lg, groups = 64u >> lg;
     const uint32_t g = lane >> lg;
     uint32_t *hist_lds = smem + D->lds_hist;

@@ -63,8 +63,8 @@ def run_batch(spec, seed, runs=1, **opt):
     return outs, cfg
 
 
-@pytest.mark.parametrize("kern", [dict(kernel=1), dict(kernel=2, group_lanes=16), dict(kernel=2, group_lanes=32)],
-                         ids=["lane", "coop16", "coop32"])
+@pytest.mark.parametrize("kern", [dict(kernel=1), dict(kernel=2, group_lanes=16), dict(kernel=2, group_lanes=32),
+                                  dict(kernel=2)], ids=["lane", "coop16", "coop32", "coop_per_instance"])
 def test_mixed_batch_matches_oracle_with_graph_replays(kern):
     spec = mixed_batch()
     base = 40
@@ -77,9 +77,13 @@ def test_mixed_batch_matches_oracle_with_graph_replays(kern):
     if kern["kernel"] == 1:
         assert set(cfg["placement"].tolist()) >= {1, 3}
         assert (cfg["wg_slots"] < 256).any() and (cfg["wg_slots"] == 256).any()
-    else:
+    elif "group_lanes" in kern:
         assert ((cfg["placement"] & 5) == 5).all()
         assert (cfg["wg_slots"] == 256 // kern["group_lanes"]).all()
+    else:
+        # group sizes of 16, 32 or 64 lanes, one per instance
+        assert ((cfg["placement"] & 5) == 5).all()
+        assert set(cfg["wg_slots"].tolist()) <= {16, 8, 4}
     for i, (inst, budget, slots, k, m) in enumerate(spec):
         orc, nb = P.oracle_run(inst, budget, slots, k, m, seed=11, instance_id=base + i)
         P.check(outs[-1][i], orc, budget, slots, m)
@@ -126,7 +130,8 @@ def test_batch_invariant_to_launch_shape():
               dict(plan=4, wg_per_cu=1), dict(kernel=1, use_graph=0, ticket_slots=8),
               dict(kernel=1, narrow_lanes=256), dict(kernel=1, narrow_lanes=32, wg_per_cu=2),
               dict(kernel=2, wg_per_cu=3, ticket_slots=1, group_lanes=64),
-              dict(kernel=2, plan=2, use_graph=0, group_lanes=8)]
+              dict(kernel=2, plan=2, use_graph=0, group_lanes=8),
+              dict(kernel=2, wg_per_cu=1), dict(kernel=2, wg_per_cu=4, ticket_slots=2)]
     for sh in shapes:
         got, cfg = run_batch(spec, seed=5, **sh)
         if "wg_per_cu" in sh:
@@ -135,7 +140,7 @@ def test_batch_invariant_to_launch_shape():
             assert not cfg["placement"].any()
         if sh.get("narrow_lanes") == 256:
             assert (cfg["wg_slots"] == 256).all() and (cfg["placement"] == 0).any()
-        if sh.get("kernel") == 2:
+        if sh.get("kernel") == 2 and "group_lanes" in sh:
             assert (cfg["wg_slots"] == 256 // sh["group_lanes"]).all()
         for a, b in zip(ref[0], got[0]):
             assert np.array_equal(a["bucket_sum"], b["bucket_sum"]), sh
@@ -272,6 +277,9 @@ def test_uneven_batch_capped_every_instance():
     outs, cfg = run_batch(spec, seed=1, keep_slot_records=1, keep_mismatch=1, cap_sweeps=20)
     res = outs[0]
     assert sum(r["stats"]["cap_hits"] for r in res) > 0
+    # one launch, group sizes chosen per instance (small instances run
+    # groups of 16 lanes, the largest groups of 64)
+    assert len({r["stats"]["group_lanes"] for r in res}) > 1
     for i, (inst, budget, slots, k, m) in enumerate(spec):
         print(f"[oracle] capped uneven instance {i}: n={inst.n} m={inst.m} slots={slots}", flush=True)
         orc, _ = P.oracle_run(inst, budget, slots, k, m, seed=1, instance_id=i, max_steps=20 * inst.n)

@@ -233,3 +233,26 @@ def test_paper_shaped_full_size(kern):
     gpu, orc = compare(inst, rp.budget, rp.slots, rp.k, rp.m, rp.seed, **kern)
     assert gpu["stats"]["placement"] & 1          # chain state in LDS
     assert gpu["stats"]["nstar_max"] >= 3
+
+
+# Slots whose events touch more clones than their group has lanes: the
+# group's per-lane numerator entries are evicted into its global row in
+# turn, and the slot's flush goes through the touched list, or scans the row
+# once the list has overflowed (its capacity here is 64 entries)
+@pytest.mark.parametrize("design", [(300, 40, 3, 10, 0.1, 0.1), (600, 60, 4, 12, 0.15, 0.15)], ids=["n300", "n600"])
+@pytest.mark.parametrize("lanes", [8, 16, 64])
+def test_numerator_entries_evicted(design, lanes):
+    from oracle import oracle as O
+    n = design[0]
+    inst = I.make_instance("evict", *design, prior=design[3] / n, seed=3)
+    k, m, cap = n // 10, n, 20 * n
+    # how many clones a replication leaves a nonzero numerator on (a lower
+    # bound on the clones its events touch), on the oracle
+    M = O.Model(inst)
+    touched = np.array([(M.trace(p, 1, max_len=cap, k=k, m=m, budget=0, slots=1, seed=5, max_steps=cap)["numer"]
+                         != 0).sum() for p in range(16)])
+    if lanes < 64 or n == 600:
+        assert (touched > lanes).mean() >= 0.25
+    slots = 256
+    gpu, _ = compare(inst, slots * 3 * m, slots, k, m, seed=5, max_steps=cap, kernel=2, group_lanes=lanes)
+    assert gpu["stats"]["group_lanes"] == lanes
