@@ -181,10 +181,11 @@ typedef struct mcpd_tune_entry {
     uint32_t narrow_lanes;        /* least lanes of a narrow LDS layout (0 = wide
                                      layouts only)                              */
     uint32_t kernel;              /* 1 = lane kernel, 2 = cooperative kernel    */
-    uint32_t group_lanes;         /* lanes per slot (1 for the lane kernel; 0 =
-                                     chosen per instance, as group_lanes = 0
-                                     of mcpd_run_opts)                          */
-    uint32_t reserved;
+    uint32_t group_lanes;         /* lanes per slot (1 for the lane kernel), or
+                                     with per_instance the least an instance
+                                     may take                                   */
+    uint32_t per_instance;        /* 1 = group sizes chosen per instance (as
+                                     group_lanes = 0 of mcpd_run_opts does)     */
     double ms;                    /* sampler time of one full run               */
 } mcpd_tune_entry;
 

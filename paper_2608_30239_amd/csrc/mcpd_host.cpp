@@ -1559,14 +1559,15 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
                 cands.push_back(c);
             }
         }
-        // group sizes per instance (from 16 lanes up), at every workgroup count that fits
-        if (!L.opts.group_lanes) {
-            const uint32_t top = coop_wg(L, most, 4, true);
+        // group sizes per instance (from 16 or from 32 lanes up), at every
+        // workgroup count that fits
+        for (uint32_t lo = 4; lo <= 5 && !L.opts.group_lanes; ++lo) {
+            const uint32_t top = coop_wg(L, most, lo, true);
             for (uint32_t w = top; w >= 1; --w) {
                 if (L.opts.wg_per_cu && w != L.opts.wg_per_cu) continue;
                 Config c;
                 c.coop = true;
-                c.group_log2 = 4;
+                c.group_log2 = lo;
                 c.mixed = true;
                 c.wg_per_cu = w;
                 c.spl = L.opts.ticket_slots ? L.opts.ticket_slots : 4u;
@@ -1589,7 +1590,7 @@ int mcpd_batch_tune(mcpd_batch *b, uint64_t seed, mcpd_tune_entry *entries, uint
         ms = 0.5 * (ms + L.last_ms);
         if (entries && done < cap)
             entries[done] = mcpd_tune_entry{c.wg_per_cu, c.spl, c.narrow, c.coop ? 2u : 1u,
-                                            c.coop ? (c.mixed ? 0u : 1u << c.group_log2) : 1u, 0u, ms};
+                                            c.coop ? 1u << c.group_log2 : 1u, c.mixed ? 1u : 0u, ms};
         ++done;
         if (ms < best_ms) { best_ms = ms; best = c; }
     }

@@ -85,7 +85,7 @@ class RunStats(C.Structure):
 
 class TuneEntry(C.Structure):
     _fields_ = [("wg_per_cu", C.c_uint32), ("ticket_slots", C.c_uint32), ("narrow_lanes", C.c_uint32),
-                ("kernel", C.c_uint32), ("group_lanes", C.c_uint32), ("reserved", C.c_uint32),
+                ("kernel", C.c_uint32), ("group_lanes", C.c_uint32), ("per_instance", C.c_uint32),
                 ("ms", C.c_double)]
 
 
@@ -363,7 +363,7 @@ class Batch:
         _check(load().mcpd_batch_tune(self.h, seed, ent, cap, C.byref(cnt)), "mcpd_batch_tune")
         return [dict(wg_per_cu=int(e.wg_per_cu), ticket_slots=int(e.ticket_slots),
                      narrow_lanes=int(e.narrow_lanes), kernel=int(e.kernel),
-                     group_lanes=int(e.group_lanes), ms=float(e.ms))
+                     group_lanes=int(e.group_lanes), per_instance=bool(e.per_instance), ms=float(e.ms))
                 for e in ent[:cnt.value]]
 
     def config(self):
