@@ -58,11 +58,14 @@ enum Place : uint32_t { PLACE_STATE_LDS = 1, PLACE_TABLES_LDS = 2, PLACE_COOP = 
 // Wavefronts of a workgroup of the cooperative kernel.
 constexpr uint32_t COOP_WAVES_PER_WG = WG_LANES / 64;
 
-// Wavefronts per SIMD the cooperative kernel is compiled for: 5 (at most 96
-// VGPRs) for rows of up to 5 entries, 4 for wider rows, whose extra
-// registers would otherwise spill.  With 4 SIMDs per CU, that many of its
-// workgroups fit on a CU.
-__host__ __device__ constexpr uint32_t coop_waves_per_simd(int f) { return fmt_entries(f) <= 5 ? 5u : 4u; }
+// Wavefronts of the cooperative kernel per SIMD: 5 (at most 96 VGPRs) for
+// rows of up to 5 entries and for 16-bit rows of 8 entries, which fit them;
+// 4 for the other wide rows, whose extra registers would otherwise spill.
+// With 4 SIMDs per CU, that many of its workgroups fit on a CU.
+__host__ __device__ constexpr uint32_t coop_waves_per_simd(int f)
+{
+    return (fmt_entries(f) <= 5 || f == FMT_U16_8) ? 5u : 4u;
+}
 
 // One instance of a launch, in device memory.  The kernel reads it with
 // scalar loads after a workgroup has taken a ticket for the instance.

@@ -251,16 +251,25 @@ int pick_format(bool wide, int need)
 }
 
 // Clone rows of an instance in format fmt (entry = pool | outcome << top
-// bit, ascending, padded with all-ones), uploaded on first use.  Rows of
-// FMT_U8_5 have three spare bytes; the last holds the outcome bits of the
-// entries (bit e = outcome of entry e).
+// bit, ascending; padding entries name pool m, one past the last pool),
+// uploaded on first use.  Rows of FMT_U8_5 have three spare bytes; the last
+// holds the outcome bits of the entries (bit e = outcome of entry e).
 int rows_for(mcpd_instance *I, int fmt, const uint32_t **out)
 {
     if (!I->d_rows[fmt]) {
         const size_t rb = (size_t)fmt_row_bytes(fmt);
+        const int ne = fmt_entries(fmt);
         std::vector<uint8_t> rowb((size_t)I->n * rb, 0xFFu);
         for (int32_t i = 0; i < I->n; ++i) {
             const size_t at = (size_t)i * rb;
+            for (int pos = 0; pos < ne; ++pos) {
+                if (!fmt_wide(fmt)) {
+                    rowb[at + pos] = (uint8_t)I->m;
+                } else {
+                    const uint16_t v = (uint16_t)I->m;
+                    std::memcpy(&rowb[at + 2 * pos], &v, 2);
+                }
+            }
             uint32_t om = 0;
             for (int32_t e = I->row_ptr[i]; e < I->row_ptr[i + 1]; ++e) {
                 const uint32_t j = (uint32_t)I->pool_idx[e], yj = I->y[j];

@@ -154,7 +154,9 @@ struct Row {
         if constexpr (WIDE) return (w[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu;
         else return (w[e >> 2] >> ((e & 3) * 8)) & 0xFFu;
     }
-    __device__ __forceinline__ static bool valid(uint32_t v) { return WIDE ? v != 0xFFFFu : v != 0xFFu; }
+    // Padding entries name pool m, one past the last pool (whose counts are a
+    // sentinel in the cooperative kernel's layout).
+    __device__ __forceinline__ static bool valid(uint32_t v, uint32_t m) { return pool(v) != m; }
     __device__ __forceinline__ static uint32_t pool(uint32_t v) { return WIDE ? (v & 0x7FFFu) : (v & 0x7Fu); }
     __device__ __forceinline__ static uint32_t outcome(uint32_t v) { return WIDE ? (v >> 15) : (v >> 7); }
 };
@@ -219,7 +221,7 @@ struct Sampler {
 #pragma unroll
                 for (int x = 0; x < Row<F>::NE; ++x) {
                     const uint32_t v = rr.raw(x);
-                    if (!Row<F>::valid(v)) continue;
+                    if (!Row<F>::valid(v, (uint32_t)D->m)) continue;
                     const uint32_t j = Row<F>::pool(v);
                     cnt(j >> 1) += 0x0101u << ((j & 1u) << 4);
                 }
@@ -332,7 +334,7 @@ struct Sampler {
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
             const uint32_t v = rc.raw(e);
-            ld.cw[e] = cnt((R::valid(v) ? R::pool(v) : 0u) >> 1);
+            ld.cw[e] = cnt((R::valid(v, (uint32_t)D->m) ? R::pool(v) : 0u) >> 1);
         }
         return ld;
     }
@@ -356,7 +358,7 @@ struct Sampler {
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
             const uint32_t v = rc.raw(e);
-            const bool ok = R::valid(v);
+            const bool ok = R::valid(v, (uint32_t)D->m);
             const uint32_t o = R::outcome(v);
             const uint32_t c = ld.cw[e] >> ((R::pool(v) & 1u) << 4);
             const bool fx = ok && (c & 0xFFu) == xi;
@@ -383,7 +385,7 @@ struct Sampler {
 #pragma unroll
             for (int e = 0; e < R::NE; ++e) {
                 const uint32_t v = rc.raw(e);
-                if (!R::valid(v)) continue;
+                if (!R::valid(v, (uint32_t)D->m)) continue;
                 const uint32_t j = R::pool(v);
                 const uint32_t cs = (j & 1u) << 4;
                 const uint32_t delta = ((uint32_t)dx << cs) + ((uint32_t)dy << (cs + 8u));
@@ -821,7 +823,6 @@ __global__ void __launch_bounds__(256) sampler_kernel(LaunchArgs a)
 // every group keeps its own in LDS, and a pair that takes very long to meet
 // advances many draws per step.  Smaller groups waste fewer speculative
 // draws when changes are frequent; larger ones go further when they are rare.
-constexpr uint32_t COOP_WAVES = WG / 64;   // wavefronts per workgroup
 
 struct GroupSlot {
     uint32_t mode, p, r, t, nret, tau, target, lim, stop, lc, cptr;
@@ -1034,7 +1035,7 @@ struct Coop {
 #pragma unroll
                     for (int x = 0; x < R::NE; ++x) {
                         const uint32_t v = rr.raw(x);
-                        if (!R::valid(v)) continue;
+                        if (!R::valid(v, (uint32_t)D->m)) continue;
                         const uint32_t j = R::pool(v);
                         count_add(j, 1, 1);
                     }
@@ -1265,15 +1266,15 @@ struct Coop {
         const uint32_t bw = st[bw_idx];
         // (X, Y) counts of each entry's pool: X in the low half (a 32-bit
         // word per pool) or the low byte (a 16-bit pair per pool)
+        // (padding entries name pool m, whose counts are the all-ones sentinel)
         const uint16_t *c16 = reinterpret_cast<const uint16_t *>(cst);
-        const uint32_t m = D->m;
         constexpr uint32_t CB = WPP ? 16u : 8u;          // bits of one count
         constexpr uint32_t CM = (1u << CB) - 1u;
         uint32_t cp[R::NE];
 #pragma unroll
         for (int e = 0; e < R::NE; ++e) {
             const uint32_t j = R::pool(rc.raw(e));
-            cp[e] = WPP ? cst[j < m ? j : m] : (uint32_t)c16[j < m ? j : m];
+            cp[e] = WPP ? cst[j] : (uint32_t)c16[j];
         }
         const uint32_t sh = (I & 15u) << 1;
         const uint32_t xi = (bw >> sh) & 1u;
@@ -1333,7 +1334,7 @@ struct Coop {
 #pragma unroll
             for (int e = 0; e < R::NE; ++e) {
                 const uint32_t v = rc.raw(e);
-                if (!R::valid(v)) continue;
+                if (!R::valid(v, (uint32_t)D->m)) continue;
                 count_add(R::pool(v), dx, dy);
             }
             int dmu = 0;
