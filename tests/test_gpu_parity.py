@@ -241,7 +241,8 @@ def test_paper_shaped_full_size(kern):
 # once the list has overflowed (its capacity here is 64 entries)
 @pytest.mark.parametrize("design", [(300, 40, 3, 10, 0.1, 0.1), (600, 60, 4, 12, 0.15, 0.15)], ids=["n300", "n600"])
 @pytest.mark.parametrize("lanes", [8, 16, 64])
-def test_numerator_entries_evicted(design, lanes):
+@pytest.mark.parametrize("init_mode", [0, 1], ids=["zero_start", "prior_start"])
+def test_numerator_entries_evicted(design, lanes, init_mode):
     from oracle import oracle as O
     n = design[0]
     inst = I.make_instance("evict", *design, prior=design[3] / n, seed=3)
@@ -254,5 +255,8 @@ def test_numerator_entries_evicted(design, lanes):
     if lanes < 64 or n == 600:
         assert (touched > lanes).mean() >= 0.25
     slots = 256
-    gpu, _ = compare(inst, slots * 3 * m, slots, k, m, seed=5, max_steps=cap, kernel=2, group_lanes=lanes)
+    # the prior start (init_mode 1) also puts the window terms of the clones
+    # that start positive in the row and the touched list before any event
+    gpu, _ = compare(inst, slots * 3 * m, slots, k, m, seed=5, max_steps=cap, kernel=2, group_lanes=lanes,
+                     init_mode=init_mode)
     assert gpu["stats"]["group_lanes"] == lanes
