@@ -151,11 +151,22 @@ def score_weights(dec):
     dec.set_weights(None)
 
 
-def learned_weights(net, alpha=0.5):
+# The floor of the learned weights, w = (1 - FLOOR) softmax(c + f) + FLOOR / n:
+# chosen by choose_floor on floor_validation_set() for the shipped network
+# (the largest geometric-mean efficiency gain over the score weights, 1024
+# runs per weighting and instance).  Any floor in (0, 1] keeps the weights
+# fixed and positive; at 0.5, the score weights' own floor, a network whose
+# output is zero reproduces the score weights.
+FLOOR = 0.05
+FLOOR_CANDIDATES = (0.02, 0.05, 0.1, 0.2, 0.35, 0.5, 0.65, 0.8)
+TRAINING_FLOOR = 0.5   # the floor at which main() compares its targets
+
+
+def learned_weights(net, alpha=FLOOR):
     return lambda dec: net.apply(dec, alpha)
 
 
-def judge(dec, net, rp, frac=16, seed=1 << 20, alpha=0.5):
+def judge(dec, net, rp, frac=16, seed=1 << 20, alpha=FLOOR):
     """The score weights as judge: a pilot on 1/frac of the slots at the same
     horizon B with each weighting (slots are i.i.d., so the per-slot variance
     is the same as in the full run), then the weighting with the larger
@@ -198,6 +209,30 @@ def evaluation_set():
     return [I.paper_shaped()] + [I.heldout_large(1000 + i) for i in range(4)]
 
 
+def floor_validation_set():
+    """Four further 20000-clone instances, drawn like the evaluation set's
+    but from other seeds, for choosing the floor of the learned weights."""
+    return [I.heldout_large(2010 + i) for i in range(4)]
+
+
+def choose_floor(net, floors=FLOOR_CANDIDATES, nrep=1024, instances=None, log=print):
+    """The floor with the largest geometric mean of the efficiency gain
+    over the score weights on the floor-validation instances; returns
+    (floor, {floor: [gain per instance]})."""
+    gains = {a: [] for a in floors}
+    for inst, rp in (instances or floor_validation_set()):
+        cmp_ = Comparison(inst, rp, nref=nrep)
+        cmp_.measure("score", score_weights, nrep)
+        for a in floors:
+            cmp_.measure(f"floor{a}", learned_weights(net, a), nrep)
+            gains[a].append(cmp_.gain(f"floor{a}"))
+        log(f"floor validation {inst.name}: " + ", ".join(f"{a}: {g[-1]:.2f}" for a, g in gains.items()))
+        cmp_.dec.set_weights(None)
+        cmp_.close()
+    geo = {a: float(np.exp(np.mean(np.log(np.maximum(g, 1e-12))))) for a, g in gains.items()}
+    return max(geo, key=geo.get), gains
+
+
 # (rho, eps) of the target t ~ exp((1 - rho) c) (v + eps)^rho
 CANDIDATES = ((0.1, 1e-3), (0.15, 1e-3), (0.2, 1e-3), (0.3, 1e-3), (0.15, 1e-2), (0.3, 1e-2))
 
@@ -219,7 +254,7 @@ def main(out=TRAINED, steps=600, nrep=12, log=print):
         cmp_ = Comparison(inst, rp, nref=16)
         cmp_.measure("score", score_weights, nrep)
         for c, net in nets.items():
-            cmp_.measure(str(c), learned_weights(net), nrep)
+            cmp_.measure(str(c), learned_weights(net, TRAINING_FLOOR), nrep)
             gains[c].append(cmp_.gain(str(c), key="var_efficiency"))
         log(f"validation {inst.name}: " + ", ".join(f"{c}: {g[-1]:.2f}" for c, g in gains.items()))
         cmp_.close()

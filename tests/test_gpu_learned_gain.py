@@ -5,6 +5,8 @@ four 20000-clone instances (the network saw only the uneven batch).  Equal
 budget means equal progress units and slots; the gain is the ratio of
 1 / (MSE x device seconds), MSE against the mean of 1024 independent
 reference runs with its own variance removed, over 1024 runs per weighting.
+The learned weights use the floor selection.FLOOR, chosen on four other
+20000-clone instances (selection.choose_floor), not on these.
 
 Every run has a fixed seed, so every figure here is a function of the
 inputs and the shipped network alone.  On the 20000-clone instances the
@@ -37,24 +39,25 @@ def test_trained_network_against_score_weights_on_the_evaluation_set():
         assert np.isfinite(r["gain"]) and r["gain"] > 0
         lo, hi = r["gain_ci90"]
         assert lo <= r["gain"] <= hi
-        # the typical run is not made worse anywhere
-        assert r["median_gain"] > 0.8
+        # the typical run gains everywhere
+        assert r["median_gain"] > 1.0
     print(f"geometric mean gain {res['gain_geomean']:.2f}", flush=True)
     # the paper-shaped instance: a clear win, its whole interval above one
     k = rows["knill1298x97"]
-    assert k["gain"] > 1.3 and k["gain_ci90"][0] > 1.0
-    assert res["gain_geomean"] > 1.0
+    assert k["gain"] > 1.5 and k["gain_ci90"][0] > 1.0
+    assert res["gain_geomean"] > 1.5
 
 
 def test_zero_residual_network_is_the_score_weights():
-    """The fallback: a network whose output is zero reproduces the score
-    weights exactly, hence the same runs bit for bit."""
+    """The fallback: a network whose output is zero, at the score weights'
+    own floor of 1/2, reproduces the score weights exactly, hence the same
+    runs bit for bit."""
     inst, rp = I.paper_shaped()
     net = N.Mlp(np.zeros(N.MLP_PARAMS, np.float32))
     dec = N.Decoder(inst)
     try:
         a = dec.run(rp.budget // 16, rp.slots // 16, rp.k, rp.m, 5)
-        net.apply(dec)
+        net.apply(dec, 0.5)
         b = dec.run(rp.budget // 16, rp.slots // 16, rp.k, rp.m, 5)
     finally:
         dec.close()
