@@ -211,7 +211,7 @@ def learned_line(nref: int, nrep: int):
             "var_gain", "tau_max_p99")
     return dict(instances={r["instance"]: {k: r[k] for k in keep} for r in res["rows"]},
                 gain_geomean=res["gain_geomean"], median_gain_geomean=res["median_gain_geomean"],
-                reference_runs=nref, runs=nrep,
+                reference_runs=nref, runs=nrep, weight_floor=S.FLOOR,
                 metric="efficiency 1/(MSE x device seconds), learned over score weights; 90% bootstrap interval")
 
 
