@@ -357,7 +357,7 @@ class Batch:
         return out
 
     def tune(self, seed=0):
-        cap = 32
+        cap = 64
         ent = (TuneEntry * cap)()
         cnt = C.c_uint32()
         _check(load().mcpd_batch_tune(self.h, seed, ent, cap, C.byref(cnt)), "mcpd_batch_tune")
